@@ -1,0 +1,176 @@
+"""Oracle, the method step by step (plain CPU, float64): Fermi-operator
+expansion, matrix powers and eigenvalues in an interval, on fixed patterns.
+
+TEST INFRASTRUCTURE ONLY.  Steps follow the paper in its order:
+
+ 1. bounds of S (given, or Gershgorin's upper bound and a Lanczos lower bound);
+ 2. X = S^{-1/2} by the truncated chain on S~ = sigma_S (S - tau_S I)
+    (Sec. "Matrix powers": the FOE machinery with f(x) = x^a);
+ 3. H' = P_H o (X P_K o (H X)), then symmetrised (Sec. "Fermi Operator
+    Expansion": the input is replaced by S^-1/2 H S^-1/2; reading R3 applies
+    the scale and shift in that orthogonal frame, reading R4 keeps H' on the
+    pattern of H, the "sparser Hamiltonian" of Sec. "Fixed versus variable
+    sparsity");
+ 4. bounds of H' (given, or Gershgorin), sigma and tau by Eq. 3;
+ 5. n_pl by Eq. 7 at mu = tau (given values skip this);
+ 6. the chain on H~' with the moments t_k = Tr T_k;
+ 7. mu by bisection on N(mu) = sum' c_k(mu) t_k (= Tr K'(mu) by linearity of
+    Eq. 1; reading R9), unless mu is given;
+ 8. K' = sum' c_k(mu) T_k by a second pass of the chain;
+ 9. K = P_K o (X P_K o (K' X)), the post-processing S^-1/2 p S^-1/2.
+
+Every value array is in block-CSR order [nnzb, b, b] at the interface and is
+converted to scalar CSR inside; the chain itself is csr_chain.c.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import chebyshev as cb
+from .csr import (Csr, block_pattern_to_csr, block_values_to_csr, chebyshev,
+                  csr_values_to_block, masked_spgemm)
+
+
+class BlockMat:
+    """A block-CSR matrix given to the oracle: pattern + [nnzb, b, b] values."""
+
+    def __init__(self, nb, b, row_ptr, col_idx, val=None):
+        self.nb, self.b = int(nb), int(b)
+        self.row_ptr = np.asarray(row_ptr, dtype=np.int64)
+        self.col_idx = np.asarray(col_idx, dtype=np.int32)
+        self.val = None if val is None else np.asarray(val, dtype=np.float64).reshape(-1, b, b)
+        self._csr = None
+
+    def csr(self) -> Csr:
+        if self._csr is None:
+            self._csr = block_pattern_to_csr(self.nb, self.b, self.row_ptr, self.col_idx)
+        c = Csr(self._csr.n, self._csr.rp, self._csr.ci)
+        if self.val is not None:
+            c.v = block_values_to_csr(self.nb, self.b, self.row_ptr, self.val)
+        return c
+
+    def pattern_csr(self) -> Csr:
+        if self._csr is None:
+            self._csr = block_pattern_to_csr(self.nb, self.b, self.row_ptr, self.col_idx)
+        return self._csr
+
+    def to_block(self, v_csr) -> np.ndarray:
+        return csr_values_to_block(self.nb, self.b, self.row_ptr, v_csr)
+
+
+def scaled(A: Csr, lo: float, hi: float) -> Csr:
+    """Eq. 2: sigma (A - tau I) with sigma, tau from Eq. 3."""
+    sigma, tau = cb.scale_shift(lo, hi)
+    r = np.repeat(np.arange(A.n), np.diff(A.rp))
+    v = A.v.copy()
+    v[r == A.ci] -= tau
+    return A.with_values(sigma * v)
+
+
+def symmetrised(A: Csr) -> Csr:
+    M = A.to_scipy()
+    Ms = (M + M.T) * 0.5
+    return A.with_values(np.asarray(Ms[np.repeat(np.arange(A.n), np.diff(A.rp)), A.ci]).ravel())
+
+
+def transpose_on(A: Csr) -> Csr:
+    """A^T on the same (symmetric) pattern."""
+    M = A.to_scipy().T.tocsr()
+    return A.with_values(np.asarray(M[np.repeat(np.arange(A.n), np.diff(A.rp)), A.ci]).ravel())
+
+
+def s_bounds(S: Csr, lanczos_k: int = 60, margin: float = 1e-3) -> tuple[float, float]:
+    """Upper: Gershgorin.  Lower: Gershgorin if positive, else the smallest
+    Lanczos Ritz value minus its residual and a relative margin."""
+    glo, ghi = cb.gershgorin(S.to_scipy())
+    if glo > 0:
+        return glo, ghi
+    M = S.to_scipy()
+    tmin, tmax, rmin, rmax = cb.lanczos_extremes(lambda x: M @ x, S.n, min(lanczos_k, S.n))
+    lo = tmin - rmin - margin * (ghi - tmin)
+    if lo <= 0:
+        raise ValueError("S is not positive definite to within the Lanczos estimate")
+    return lo, ghi
+
+
+def matrix_power(S: BlockMat, a: float, pattern: BlockMat, bounds=None, n_pl=None,
+                 tol_fit: float = 1e-12, extra_powers=()):
+    """Sec. "Matrix powers": S^a on `pattern` by the chain with f = x^a.
+    Returns (values [nnzb, b, b], info) (and extra powers from the same chain
+    when `extra_powers` is given: a dict a' -> values)."""
+    Sc = S.csr()
+    K = pattern.pattern_csr()
+    lo, hi = bounds if bounds is not None else s_bounds(Sc)
+    powers = (a,) + tuple(extra_powers)
+    if n_pl is None:
+        n_pl = max(cb.degree(cb.power_fn(p), lo, hi, tol_fit) for p in powers)
+    coefs = np.stack([cb.cheb_coeffs(cb.power_fn(p), lo, hi, n_pl) for p in powers])
+    acc, mom = chebyshev(scaled(Sc, lo, hi), K, n_pl, coefs)
+    # left-multiplication chain -> values are those of p(S~) directly
+    outs = [pattern.to_block(acc[q]) for q in range(len(powers))]
+    info = dict(lo=lo, hi=hi, n_pl=n_pl, moments=mom)
+    if extra_powers:
+        return outs[0], info, {p: o for p, o in zip(extra_powers, outs[1:])}
+    return outs[0], info
+
+
+def orthogonal_frame(H: BlockMat, S: BlockMat, pattern: BlockMat, s_bnds=None, n_pl_s=None,
+                     tol_fit_s: float = 1e-12):
+    """Steps 1-3: returns (X on P_K as Csr, H' on P_H as Csr, info)."""
+    Xv, sinfo = matrix_power(S, -0.5, pattern, bounds=s_bnds, n_pl=n_pl_s, tol_fit=tol_fit_s)
+    K = pattern.pattern_csr()
+    X = K.with_values(block_values_to_csr(pattern.nb, pattern.b, pattern.row_ptr, Xv))
+    Hc = H.csr()
+    Z = K.with_values(masked_spgemm(Hc, X, K))          # P_K o (H X)
+    Hp = Hc.with_values(masked_spgemm(X, Z, Hc))        # P_H o (X Z)
+    Hp = symmetrised(Hp)
+    return X, Hp, sinfo
+
+
+def fermi_operator(H: BlockMat, S: BlockMat, pattern: BlockMat, n_e: float, kT: float,
+                   smearing: str = "erfc", s_bounds_=None, n_pl_s=None, h_bounds=None,
+                   n_pl=None, mu=None, tol_fit: float = 1e-12, tol_fit_s: float = 1e-12,
+                   tol_ne: float | None = None):
+    """Steps 1-9.  Returns (K values [nnzb_K, b, b], info dict)."""
+    X, Hp, sinfo = orthogonal_frame(H, S, pattern, s_bounds_, n_pl_s, tol_fit_s)
+    K = pattern.pattern_csr()
+    lo, hi = h_bounds if h_bounds is not None else cb.gershgorin(Hp.to_scipy())
+    sigma, tau = cb.scale_shift(lo, hi)
+    occ = cb.occ_erfc if smearing == "erfc" else cb.occ_fermi_dirac
+    if n_pl is None:
+        n_pl = cb.degree(lambda e: occ(e, tau, kT), lo, hi, tol_fit)
+    Ht = scaled(Hp, lo, hi)
+    _, mom = chebyshev(Ht, K, n_pl, None)
+    it = 0
+    if mu is None:
+        tol_ne = 1e-8 * n_e if tol_ne is None else tol_ne
+        mu, it = cb.bisect_mu(mom, lo, hi, kT, n_e, tol_ne, smearing)
+    c = cb.cheb_coeffs(lambda e: occ(e, mu, kT), lo, hi, n_pl)
+    acc, _ = chebyshev(Ht, K, n_pl, c[None, :])
+    Kp = K.with_values(acc[0])
+    W = K.with_values(masked_spgemm(Kp, X, K))          # P_K o (K' X)
+    Kv = masked_spgemm(X, W, K)                          # P_K o (X W)
+    Kfin = K.with_values(Kv)
+    Sc = S.csr()
+    trKS = float(Kfin.to_scipy().multiply(Sc.to_scipy()).sum())
+    info = dict(mu=mu, lo=lo, hi=hi, n_pl=n_pl, n_pl_s=sinfo["n_pl"], s_lo=sinfo["lo"],
+                s_hi=sinfo["hi"], moments=mom, bisect_iters=it, trKS=trKS,
+                ne_chain=cb.trace_from_moments(c, mom))
+    return pattern.to_block(Kv), info
+
+
+def eigs_in_interval(H: BlockMat, S: BlockMat, pattern: BlockMat, e_lo: float, e_hi: float,
+                     width: float = 1e-3, s_bounds_=None, n_pl_s=None, h_bounds=None,
+                     n_pl=None, tol_fit: float = 1e-6, smearing: str = "erfc"):
+    """Sec. "Extraction of selected eigenvalues": chain moments on H~', then the
+    mu at which the occupation is N - 1/2 for each N inside [e_lo, e_hi]."""
+    X, Hp, sinfo = orthogonal_frame(H, S, pattern, s_bounds_, n_pl_s)
+    K = pattern.pattern_csr()
+    lo, hi = h_bounds if h_bounds is not None else cb.gershgorin(Hp.to_scipy())
+    sigma, tau = cb.scale_shift(lo, hi)
+    occ = cb.occ_erfc if smearing == "erfc" else cb.occ_fermi_dirac
+    if n_pl is None:
+        n_pl = cb.degree(lambda e: occ(e, tau, width), lo, hi, tol_fit)
+    _, mom = chebyshev(scaled(Hp, lo, hi), K, n_pl, None)
+    ev = cb.eigenvalues_from_moments(mom, lo, hi, width, e_lo, e_hi, smearing)
+    return ev, dict(lo=lo, hi=hi, n_pl=n_pl, moments=mom)
