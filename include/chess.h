@@ -1,0 +1,205 @@
+/*
+ * chess.h -- C interface of the Chebyshev sparse matrix-function library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates f(M) for a sparse symmetric matrix M by the Chebyshev
+ * expansion of the paper "Efficient computation of sparse matrix functions for
+ * large scale electronic structure calculations: The CheSS library":
+ *
+ *   p(M) = c_0/2 I + sum_{j=1}^{n_pl-1} c_j T_j(M~)          (Eq. 1)
+ *   M~ = sigma (M - tau I), sigma = 2/(e_max-e_min),
+ *   tau = (e_min+e_max)/2                                     (Eqs. 2-3)
+ *   T_0 = I, T_1 = M~, T_{j+1} = 2 M~ T_j - T_{j-1}            (Eq. 4)
+ *   c_j from f at the Chebyshev nodes                         (Eq. 5)
+ *
+ * Every product is truncated to a fixed block sparsity pattern (Sec.
+ * "Truncation to a fixed sparsity pattern"), so T_j and p(M) live on the
+ * caller's output pattern.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * Matrices are block CSR with a uniform block edge b (4 or 9: one block per
+ * atom pair).  A pattern is square, its column indices are strictly increasing
+ * in each block row, every diagonal block is present and the pattern is
+ * structurally symmetric.  Values are nnzb*b*b numbers, blocks in pattern
+ * order, each block row-major.  All pointers inside chess_pattern and
+ * chess_matrix are DEVICE pointers on the context's device; pointers marked
+ * "host" below are host memory.  The caller allocates and frees every input
+ * and output; the library never frees or keeps caller memory beyond a call.
+ * Workspace (and cached per-pattern plans) belongs to the context.
+ *
+ * Work is ordered on the context's stream.  Every entry point returns after
+ * the stream has drained (results that reach the host, such as mu or
+ * eigenvalues, need that anyway), so outputs are ready on return.  A context
+ * must not be used by two threads at once.
+ *
+ * Errors: every call returns CHESS_OK (0) or a negative CHESS_E_* code; then
+ * chess_last_error() describes it and the outputs are undefined.
+ */
+#ifndef CHESS_H
+#define CHESS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CHESS_OK = 0,
+    CHESS_E_ARG = -1,         /* bad argument: null pointer, size mismatch, b mismatch */
+    CHESS_E_PATTERN = -2,     /* unsorted/asymmetric pattern, missing diagonal, pattern not nested */
+    CHESS_E_NOT_SPD = -3,     /* a non-integer power of a matrix whose lower bound is not > 0 */
+    CHESS_E_BOUNDS = -4,      /* spectral bounds still fail after max_reexpand widenings */
+    CHESS_E_NOCONV = -5,      /* mu search did not bracket or converge */
+    CHESS_E_OOM = -6,         /* device allocation failed */
+    CHESS_E_HIP = -7,         /* a HIP runtime call failed */
+    CHESS_E_UNSUPPORTED = -8, /* block edge not 4 or 9, dtype not CHESS_F64, row too long */
+    CHESS_E_CAPACITY = -9     /* eigenvalue buffer too small; *n_found holds the count */
+};
+
+/* Precision of the Chebyshev chain.  Inputs and outputs are always float64;
+ * CHESS_F32 runs the products in float32 while the weighted sums of Eq. 1,
+ * the traces and the bound/mu logic stay in float64. */
+enum { CHESS_F64 = 0, CHESS_F32 = 1 };
+
+/* Occupation function for the Fermi-operator expansion. */
+enum {
+    CHESS_ERFC = 0,        /* Eq. 11: f = 1/2 erfc((e - mu)/kT) */
+    CHESS_FERMI_DIRAC = 1  /* Eq. 9:  f = 1/(1 + exp((e - mu)/kT)) */
+};
+
+/* How bounds that are not given are estimated (Sec. "Determination of the
+ * eigenvalue bounds and polynomial degree"). */
+enum {
+    CHESS_BOUNDS_GERSHGORIN = 0, /* Gershgorin discs: rigorous, wide */
+    CHESS_BOUNDS_LANCZOS = 1     /* a few Lanczos steps plus a margin: tight, checked by Eq. 6 */
+};
+
+typedef struct chess_ctx chess_ctx;
+
+typedef struct {
+    int32_t b;              /* block edge: 4 or 9 */
+    int32_t nbrows;         /* number of block rows (= block columns) */
+    int64_t nnzb;           /* number of stored blocks */
+    const int64_t *row_ptr; /* device, nbrows+1 entries, row_ptr[0] = 0 */
+    const int32_t *col_idx; /* device, nnzb entries */
+} chess_pattern;
+
+typedef struct {
+    chess_pattern pat;
+    void *val;     /* device, nnzb*b*b values (const for inputs) */
+    int32_t dtype; /* must be CHESS_F64 */
+} chess_matrix;
+
+typedef struct {
+    int32_t precision;   /* CHESS_F64 or CHESS_F32 (default CHESS_F32) */
+    int32_t smearing;    /* CHESS_ERFC (default) or CHESS_FERMI_DIRAC */
+    int32_t bounds_mode; /* for bounds not given (default CHESS_BOUNDS_GERSHGORIN) */
+    int32_t n_pl;        /* > 0: fixed number of terms for H (or M); 0: Eq. 7 */
+    int32_t n_pl_s;      /* > 0: fixed number of terms for the S^-1/2 chain; 0: Eq. 7 */
+    int32_t store_history;   /* 1: keep every T_k (float32/float64) and recombine after the
+                                mu search (one chain pass); 0: second pass at the final mu */
+    int32_t max_reexpand;    /* widenings allowed when Eq. 6 or the growth test fails (3) */
+    int32_t lanczos_steps;   /* Lanczos steps for CHESS_BOUNDS_LANCZOS and for S (40) */
+    double tol_fit;      /* Eq. 7 threshold for H (<= 0: 1e-10 for F64, 1e-6 for F32) */
+    double tol_fit_s;    /* Eq. 7 threshold for x^-1/2 or x^a (<= 0: same rule) */
+    double tol_ne;       /* |N(mu) - N_e| target of the mu search (<= 0: 1e-8 N_e) */
+    double bounds[2];    /* spectral bounds of H' = S^-1/2 H S^-1/2 (or of M); NaN = estimate */
+    double s_bounds[2];  /* spectral bounds of S; NaN = estimate */
+    double mu;           /* not NaN: use this mu, no search */
+    double mu_bracket[2];/* not NaN: search mu here first, fall back to the full bounds */
+    double eig_width;    /* kT of the occupation used to extract eigenvalues (1e-3) */
+    double bound_margin; /* relative margin added to Lanczos bounds (0.02) */
+} chess_opts;
+
+typedef struct {
+    double mu;            /* chemical potential used */
+    double lo, hi;        /* bounds used for H' (or M) */
+    double s_lo, s_hi;    /* bounds used for S */
+    double tr_ks;         /* Tr(K S) of the returned K */
+    double ne_chain;      /* N(mu) from the moments of the chain */
+    double penalty;       /* Tr W^p of Eq. 6 for the final bounds (NaN if not evaluated) */
+    int32_t n_pl, n_pl_s; /* terms used */
+    int32_t passes;       /* chain passes over H~' */
+    int32_t bisect_iters; /* mu search iterations */
+    int32_t reexpansions; /* bound widenings */
+    int32_t chain_steps;  /* products launched in chains (all matrices) */
+    double ms_total, ms_setup, ms_s_chain, ms_transform, ms_h_chain, ms_mu, ms_post;
+    double ms_chain_kernel; /* summed device time of the H~' chain product kernel */
+} chess_info;
+
+/* Fills *opts with the defaults listed above. */
+void chess_default_opts(chess_opts *opts);
+
+/* Creates a context on `device` that orders its work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+int chess_create(chess_ctx **ctx, int device, void *hip_stream);
+int chess_destroy(chess_ctx *ctx);
+/* Message for the last non-zero return on this context (never NULL). */
+const char *chess_last_error(const chess_ctx *ctx);
+
+/*
+ * Density kernel by Fermi-operator expansion (Sec. "Fermi Operator
+ * Expansion"): K = S^-1/2 f(H~') S^-1/2 with H' = S^-1/2 H S^-1/2, f the
+ * occupation (Eq. 11 or Eq. 9) and mu chosen so that Tr K' = N_e, where
+ * K' = f(H~') (equal to Tr(KS) up to truncation).
+ *   H, S    : on the same or different patterns, each contained in `pattern`;
+ *   pattern : the kernel pattern P_K (also that of S^-1/2 and of every T_k);
+ *   K_out   : caller-allocated on exactly `pattern` (same nbrows/nnzb/b).
+ * opts may be NULL (defaults); info may be NULL.
+ */
+int chess_fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
+                         const chess_pattern *pattern, double n_electrons, double kT,
+                         chess_matrix *K_out, chess_info *info, const chess_opts *opts);
+
+/*
+ * Matrix power S^a for any real a (Sec. "Matrix powers"): the same expansion
+ * with f(x) = x^a over the spectral bounds of S; non-integer or negative a
+ * need a positive lower bound (else CHESS_E_NOT_SPD).  Sa_out is on `pattern`.
+ */
+int chess_matrix_power(chess_ctx *ctx, const chess_matrix *S, double a,
+                       const chess_pattern *pattern, chess_matrix *Sa_out,
+                       chess_info *info, const chess_opts *opts);
+
+/*
+ * Eigenvalues of H c = e S c inside [lo, hi] (Sec. "Extraction of selected
+ * eigenvalues"): the chain's trace moments give N(mu) = Tr f(H~'; mu) for any
+ * mu; eigenvalue number N is the mu with N(mu) = N - 1/2.  `pattern` is the
+ * pattern of S^-1/2 and of the T_k.  eig_out (host) receives the values in
+ * ascending order; if more than `capacity` lie in the interval the call
+ * returns CHESS_E_CAPACITY with *n_found set to the count.
+ */
+int chess_eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
+                           double lo, double hi, const chess_pattern *pattern,
+                           double *eig_out, int64_t capacity, int64_t *n_found,
+                           chess_info *info, const chess_opts *opts);
+
+/*
+ * The Chebyshev chain itself (Eqs. 1, 4), for a matrix already in [-1, 1]:
+ * M~ = sigma (M - tau I) with sigma, tau from the given bounds [lo, hi].
+ *   M       : input on a pattern contained in `pattern`;
+ *   n_pl    : terms T_0 .. T_{n_pl-1};
+ *   coef    : host, nq sets of n_pl coefficients, coef[q*n_pl + k] (nq <= 4);
+ *   acc_out : nq matrices on `pattern` receiving c_q[0]/2 I + sum c_q[k] T_k
+ *             (may be NULL when nq == 0);
+ *   moments : host, n_pl values Tr T_k (may be NULL).
+ * The products run in opts->precision.
+ */
+int chess_chebyshev(chess_ctx *ctx, const chess_matrix *M, double lo, double hi,
+                    const chess_pattern *pattern, int32_t n_pl, int32_t nq,
+                    const double *coef, chess_matrix *acc_out, double *moments,
+                    const chess_opts *opts);
+
+/*
+ * The truncated product (Sec. "Truncation to a fixed sparsity pattern"):
+ * C = P_C o (A B), computed only on C's pattern, float64.  A, B, C must have
+ * the same b and nbrows.
+ */
+int chess_masked_product(chess_ctx *ctx, const chess_matrix *A, const chess_matrix *B,
+                         chess_matrix *C);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHESS_H */

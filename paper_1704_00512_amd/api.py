@@ -1,0 +1,185 @@
+"""Python face of the C interface (include/chess.h), one function per entry
+point, same names.  PyTorch supplies device memory and the stream; every
+computation happens in libchess.so.
+
+Matrices are passed as (pattern, values): a BlockPattern holds device int64
+row_ptr / int32 col_idx tensors, values are float64 device tensors of shape
+[nnzb, b, b] (each block row-major).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_OPT_FIELDS = {name for name, _ in _lib.chess_opts._fields_}
+
+
+class ChessError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_lib.ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = _lib.ERRORS.get(code, str(code))
+
+
+@dataclass
+class BlockPattern:
+    """A block sparsity pattern resident on the GPU."""
+    b: int
+    nb: int
+    row_ptr: torch.Tensor  # int64 [nb+1], device
+    col_idx: torch.Tensor  # int32 [nnzb], device
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.col_idx.shape[0])
+
+    @staticmethod
+    def from_host(b: int, row_ptr, col_idx, device="cuda") -> "BlockPattern":
+        rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int64), device=device)
+        ci = torch.as_tensor(np.asarray(col_idx, dtype=np.int32), device=device)
+        return BlockPattern(b=int(b), nb=int(rp.shape[0] - 1), row_ptr=rp, col_idx=ci)
+
+    def c(self) -> _lib.chess_pattern:
+        return _lib.chess_pattern(self.b, self.nb, self.nnzb, self.row_ptr.data_ptr(),
+                                  self.col_idx.data_ptr())
+
+    def zeros(self) -> torch.Tensor:
+        return torch.zeros((self.nnzb, self.b, self.b), dtype=torch.float64,
+                           device=self.row_ptr.device)
+
+
+def _mat(p: BlockPattern, val: torch.Tensor) -> _lib.chess_matrix:
+    if val.dtype != torch.float64 or not val.is_cuda or not val.is_contiguous():
+        raise ValueError("matrix values must be a contiguous float64 CUDA tensor")
+    if tuple(val.shape) != (p.nnzb, p.b, p.b):
+        raise ValueError(f"values shape {tuple(val.shape)} != {(p.nnzb, p.b, p.b)}")
+    return _lib.chess_matrix(p.c(), val.data_ptr(), _lib.CHESS_F64)
+
+
+def default_opts(**kw) -> _lib.chess_opts:
+    o = _lib.chess_opts()
+    _lib.load().chess_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k not in _OPT_FIELDS:
+            raise TypeError(f"unknown option {k}")
+        if k in ("bounds", "s_bounds", "mu_bracket"):
+            arr = getattr(o, k)
+            arr[0], arr[1] = (math.nan, math.nan) if v is None else (float(v[0]), float(v[1]))
+        elif k == "mu":
+            o.mu = math.nan if v is None else float(v)
+        elif k == "precision" and isinstance(v, str):
+            o.precision = {"f64": _lib.CHESS_F64, "f32": _lib.CHESS_F32}[v]
+        elif k == "smearing" and isinstance(v, str):
+            o.smearing = {"erfc": _lib.CHESS_ERFC, "fermi_dirac": _lib.CHESS_FERMI_DIRAC}[v]
+        elif k == "bounds_mode" and isinstance(v, str):
+            o.bounds_mode = {"gershgorin": 0, "lanczos": 1}[v]
+        else:
+            setattr(o, k, v)
+    return o
+
+
+class Context:
+    """A chess_ctx on one device, ordered on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self._L = _lib.load()
+        torch.cuda.set_device(device)
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = st
+        h = ctypes.c_void_p()
+        rc = self._L.chess_create(ctypes.byref(h), device, ctypes.c_void_p(st.cuda_stream))
+        if rc != 0:
+            raise ChessError(rc, "chess_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.chess_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise ChessError(rc, self._L.chess_last_error(self._h).decode())
+
+
+def chess_fermi_operator(ctx: Context, H: torch.Tensor, pat_h: BlockPattern, S: torch.Tensor,
+                         pat_s: BlockPattern, pattern: BlockPattern, n_electrons: float,
+                         kT: float, out: torch.Tensor | None = None, **opts):
+    K = pattern.zeros() if out is None else out
+    info = _lib.chess_info()
+    o = default_opts(**opts)
+    mh, ms, mk, pk = _mat(pat_h, H), _mat(pat_s, S), _mat(pattern, K), pattern.c()
+    ctx._check(ctx._L.chess_fermi_operator(ctx._h, ctypes.byref(mh), ctypes.byref(ms),
+                                           ctypes.byref(pk), float(n_electrons), float(kT),
+                                           ctypes.byref(mk), ctypes.byref(info), ctypes.byref(o)))
+    return K, info.as_dict()
+
+
+def chess_matrix_power(ctx: Context, S: torch.Tensor, pat_s: BlockPattern, a: float,
+                       pattern: BlockPattern, out: torch.Tensor | None = None, **opts):
+    R = pattern.zeros() if out is None else out
+    info = _lib.chess_info()
+    o = default_opts(**opts)
+    ms, mr, pk = _mat(pat_s, S), _mat(pattern, R), pattern.c()
+    ctx._check(ctx._L.chess_matrix_power(ctx._h, ctypes.byref(ms), float(a), ctypes.byref(pk),
+                                         ctypes.byref(mr), ctypes.byref(info), ctypes.byref(o)))
+    return R, info.as_dict()
+
+
+def chess_eigs_in_interval(ctx: Context, H: torch.Tensor, pat_h: BlockPattern, S: torch.Tensor,
+                           pat_s: BlockPattern, lo: float, hi: float, pattern: BlockPattern,
+                           capacity: int = 1 << 16, **opts):
+    buf = (ctypes.c_double * max(capacity, 1))()
+    nf = ctypes.c_int64(0)
+    info = _lib.chess_info()
+    o = default_opts(**opts)
+    mh, ms, pk = _mat(pat_h, H), _mat(pat_s, S), pattern.c()
+    rc = ctx._L.chess_eigs_in_interval(ctx._h, ctypes.byref(mh), ctypes.byref(ms), float(lo),
+                                       float(hi), ctypes.byref(pk), buf, int(capacity),
+                                       ctypes.byref(nf), ctypes.byref(info), ctypes.byref(o))
+    ctx._check(rc)
+    return np.array(buf[: nf.value], dtype=np.float64), info.as_dict()
+
+
+def chess_chebyshev(ctx: Context, M: torch.Tensor, pat_m: BlockPattern, lo: float, hi: float,
+                    pattern: BlockPattern, n_pl: int, coef=None, want_moments: bool = True,
+                    **opts):
+    coef = np.zeros((0, n_pl)) if coef is None else np.atleast_2d(np.asarray(coef, dtype=np.float64))
+    nq = coef.shape[0]
+    if nq and coef.shape[1] != n_pl:
+        raise ValueError("coefficient sets must have n_pl entries")
+    accs = [pattern.zeros() for _ in range(nq)]
+    arr = (_lib.chess_matrix * max(nq, 1))()
+    for q in range(nq):
+        arr[q] = _mat(pattern, accs[q])
+    cbuf = np.ascontiguousarray(coef.ravel()) if nq else np.zeros(1)
+    mom = np.zeros(n_pl)
+    o = default_opts(**opts)
+    mm, pk = _mat(pat_m, M), pattern.c()
+    ctx._check(ctx._L.chess_chebyshev(
+        ctx._h, ctypes.byref(mm), float(lo), float(hi), ctypes.byref(pk), int(n_pl), int(nq),
+        cbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), arr if nq else None,
+        mom.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_moments else None,
+        ctypes.byref(o)))
+    return accs, mom
+
+
+def chess_masked_product(ctx: Context, A: torch.Tensor, pat_a: BlockPattern, B: torch.Tensor,
+                         pat_b: BlockPattern, pat_c: BlockPattern, out: torch.Tensor | None = None):
+    C = pat_c.zeros() if out is None else out
+    ma, mb, mc = _mat(pat_a, A), _mat(pat_b, B), _mat(pat_c, C)
+    ctx._check(ctx._L.chess_masked_product(ctx._h, ctypes.byref(ma), ctypes.byref(mb),
+                                           ctypes.byref(mc)))
+    return C

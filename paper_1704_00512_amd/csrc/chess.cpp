@@ -1,0 +1,1207 @@
+// Host pipeline behind the C interface of include/chess.h.
+//
+// Flow of chess_fermi_operator (Sec. "Fermi Operator Expansion"):
+//   patterns  -> validated host copies, transpose and embedding maps, and
+//                cached symbolic product plans (integer work, once per pattern)
+//   S bounds  -> Gershgorin upper bound, Lanczos lower bound (GPU SpMV)
+//   X^T       -> Chebyshev chain on S~ with f = x^-1/2 (Sec. "Matrix powers")
+//   H'        -> P_H o (X P_K o (H X)), symmetrised (two masked products)
+//   bounds    -> Gershgorin or Lanczos on H', checked afterwards by Eq. 6
+//   n_pl      -> Eq. 7 at mu = tau
+//   chain     -> Chebyshev chain on H~' with trace moments (and, optionally,
+//                every T_k kept for recombination)
+//   mu        -> bisection on N(mu) from the moments (host)
+//   K'        -> recombination of the kept T_k, or a second chain pass
+//   K         -> P_K o (X P_K o (K' X)), Tr(KS)
+//
+// All device work is on the context stream; host decisions (bounds, degree,
+// mu) read back a handful of doubles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/chess.h"
+#include "hostmath.h"
+#include "kernels.h"
+
+namespace chess {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define CHESS_THROW(code, ...)                                  \
+    do {                                                        \
+        char _buf[512];                                         \
+        std::snprintf(_buf, sizeof(_buf), __VA_ARGS__);         \
+        throw Error{code, std::string(_buf)};                   \
+    } while (0)
+
+#define HIPCHECK(expr)                                                                    \
+    do {                                                                                  \
+        hipError_t _e = (expr);                                                           \
+        if (_e != hipSuccess)                                                             \
+            CHESS_THROW(_e == hipErrorOutOfMemory ? CHESS_E_OOM : CHESS_E_HIP, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(_e), __FILE__, __LINE__);                \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t n) { alloc(n); }
+    void alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            CHESS_THROW(CHESS_E_OOM, "hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+        }
+        bytes = n;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    template <typename T>
+    T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+template <typename T>
+static void upload(DevBuf &d, const std::vector<T> &h, hipStream_t st) {
+    d.alloc(h.size() * sizeof(T));
+    if (!h.empty()) HIPCHECK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+// ---------------------------------------------------------------------------
+// patterns
+// ---------------------------------------------------------------------------
+
+struct Pattern {
+    int b = 0;
+    int nb = 0;
+    int64_t nnzb = 0;
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<int64_t> tmap;  // index of block (j, i) for block p = (i, j)
+    std::vector<int64_t> diag;  // index of block (i, i)
+    int max_row = 0;
+    DevBuf d_rp, d_ci, d_brow, d_diag, d_tmap;
+    int64_t n() const { return (int64_t)nb * b; }
+    int64_t find(int i, int j) const {
+        auto beg = ci.begin() + rp[i], end = ci.begin() + rp[i + 1];
+        auto it = std::lower_bound(beg, end, j);
+        if (it == end || *it != j) return -1;
+        return (int64_t)(it - ci.begin());
+    }
+};
+
+struct EmbedMap {
+    const Pattern *from = nullptr, *to = nullptr;
+    std::vector<int64_t> map;    // position in `to` of each block of `from`
+    DevBuf d_map, d_map_t;       // map, and map of the transposed block
+};
+
+struct ProductPlan {
+    const Pattern *a = nullptr, *bt = nullptr, *c = nullptr;
+    int dtype = 0;
+    ProductPlanDev dev;
+    DevBuf d_tile_row0, d_u_off, d_u_cols, d_u_pos, d_j_off, d_j_cols, d_j_pos;
+};
+
+}  // namespace chess
+
+struct chess_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err = "no error";
+    std::vector<std::unique_ptr<chess::Pattern>> patterns;
+    std::vector<std::unique_ptr<chess::EmbedMap>> embeds;
+    std::vector<std::unique_ptr<chess::ProductPlan>> plans;
+};
+
+namespace chess {
+
+static void validate_pattern_struct(const chess_pattern *p, const char *what) {
+    if (!p) CHESS_THROW(CHESS_E_ARG, "%s: null pattern", what);
+    if (p->b != 4 && p->b != 9) CHESS_THROW(CHESS_E_UNSUPPORTED, "%s: block edge %d (4 or 9 supported)", what, p->b);
+    if (p->nbrows <= 0 || p->nnzb < p->nbrows) CHESS_THROW(CHESS_E_ARG, "%s: nbrows %d, nnzb %lld", what, p->nbrows, (long long)p->nnzb);
+    if (!p->row_ptr || !p->col_idx) CHESS_THROW(CHESS_E_ARG, "%s: null row_ptr/col_idx", what);
+}
+
+// Copies a caller pattern to the host, validates it and returns the cached
+// entry with identical content (or a new one).
+static const Pattern *get_pattern(chess_ctx *ctx, const chess_pattern *p, const char *what) {
+    validate_pattern_struct(p, what);
+    hipStream_t st = ctx->stream;
+    std::vector<int64_t> rp((size_t)p->nbrows + 1);
+    std::vector<int32_t> ci((size_t)p->nnzb);
+    HIPCHECK(hipMemcpyAsync(rp.data(), p->row_ptr, rp.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(ci.data(), p->col_idx, ci.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    for (auto &e : ctx->patterns) {
+        if (e->b == p->b && e->nb == p->nbrows && e->nnzb == p->nnzb && e->rp == rp && e->ci == ci)
+            return e.get();
+    }
+    auto P = std::make_unique<Pattern>();
+    P->b = p->b;
+    P->nb = p->nbrows;
+    P->nnzb = p->nnzb;
+    if (rp[0] != 0 || rp[p->nbrows] != p->nnzb) CHESS_THROW(CHESS_E_PATTERN, "%s: row_ptr must start at 0 and end at nnzb", what);
+    P->diag.assign(p->nbrows, -1);
+    for (int i = 0; i < p->nbrows; ++i) {
+        if (rp[i + 1] < rp[i]) CHESS_THROW(CHESS_E_PATTERN, "%s: row_ptr decreases at row %d", what, i);
+        P->max_row = std::max<int>(P->max_row, (int)(rp[i + 1] - rp[i]));
+        for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+            const int j = ci[q];
+            if (j < 0 || j >= p->nbrows) CHESS_THROW(CHESS_E_PATTERN, "%s: column %d out of range in row %d", what, j, i);
+            if (q > rp[i] && ci[q - 1] >= j) CHESS_THROW(CHESS_E_PATTERN, "%s: columns not strictly increasing in row %d", what, i);
+            if (j == i) P->diag[i] = q;
+        }
+        if (P->diag[i] < 0) CHESS_THROW(CHESS_E_PATTERN, "%s: diagonal block missing in row %d", what, i);
+    }
+    P->rp = std::move(rp);
+    P->ci = std::move(ci);
+    P->tmap.assign((size_t)p->nnzb, -1);
+    std::vector<int32_t> brow((size_t)p->nnzb);
+    for (int i = 0; i < p->nbrows; ++i) {
+        for (int64_t q = P->rp[i]; q < P->rp[i + 1]; ++q) {
+            brow[q] = i;
+            const int64_t t = P->find(P->ci[q], i);
+            if (t < 0) CHESS_THROW(CHESS_E_PATTERN, "%s: pattern not symmetric at block (%d, %d)", what, i, P->ci[q]);
+            P->tmap[q] = t;
+        }
+    }
+    upload(P->d_rp, P->rp, st);
+    upload(P->d_ci, P->ci, st);
+    upload(P->d_brow, brow, st);
+    upload(P->d_diag, P->diag, st);
+    upload(P->d_tmap, P->tmap, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    ctx->patterns.push_back(std::move(P));
+    return ctx->patterns.back().get();
+}
+
+static const EmbedMap *get_embed(chess_ctx *ctx, const Pattern *from, const Pattern *to,
+                                 const char *what) {
+    for (auto &e : ctx->embeds)
+        if (e->from == from && e->to == to) return e.get();
+    if (from->nb != to->nb || from->b != to->b) CHESS_THROW(CHESS_E_ARG, "%s: patterns differ in size", what);
+    auto E = std::make_unique<EmbedMap>();
+    E->from = from;
+    E->to = to;
+    E->map.resize((size_t)from->nnzb);
+    std::vector<int64_t> mt((size_t)from->nnzb);
+    for (int i = 0; i < from->nb; ++i) {
+        for (int64_t q = from->rp[i]; q < from->rp[i + 1]; ++q) {
+            const int64_t p = to->find(i, from->ci[q]);
+            if (p < 0) CHESS_THROW(CHESS_E_PATTERN, "%s: block (%d, %d) not in the larger pattern", what, i, from->ci[q]);
+            E->map[q] = p;
+        }
+    }
+    for (int64_t q = 0; q < from->nnzb; ++q) mt[q] = E->map[from->tmap[q]];
+    upload(E->d_map, E->map, ctx->stream);
+    upload(E->d_map_t, mt, ctx->stream);
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    ctx->embeds.push_back(std::move(E));
+    return ctx->embeds.back().get();
+}
+
+static int pick_cmax(int dtype, int b) {
+    if (b == 4) return 4;
+    return dtype == 1 ? 2 : 1;
+}
+
+// Symbolic plan of C = P_C o (A Bt^T) (see kernels.h).
+static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Pattern *Bt,
+                                   const Pattern *C, int dtype) {
+    for (auto &e : ctx->plans)
+        if (e->a == A && e->bt == Bt && e->c == C && e->dtype == dtype) return e.get();
+    auto P = std::make_unique<ProductPlan>();
+    P->a = A;
+    P->bt = Bt;
+    P->c = C;
+    P->dtype = dtype;
+    const int b = A->b;
+    const int cmax = pick_cmax(dtype, b);
+    const size_t block_bytes = (size_t)b * b * (dtype == 1 ? 4 : 8);
+    const int budget_blocks = std::max<int>((int)(49152 / block_bytes), A->max_row);
+    std::vector<int32_t> tile_row0;
+    std::vector<int64_t> u_off{0}, j_off{0};
+    std::vector<int32_t> u_cols, j_cols;
+    std::vector<uint16_t> u_pos, j_pos;
+    int lds_ablocks = 0, max_u = 0;
+    int r = 0;
+    std::vector<int32_t> merged;
+    while (r < A->nb) {
+        const int row0 = r;
+        int64_t blocks = 0;
+        while (r < A->nb && r - row0 < cmax) {
+            const int64_t len = A->rp[r + 1] - A->rp[r];
+            if (r > row0 && blocks + len > budget_blocks) break;
+            blocks += len;
+            ++r;
+        }
+        const int c = r - row0;
+        tile_row0.push_back(row0);
+        lds_ablocks = std::max<int>(lds_ablocks, (int)blocks);
+        if (blocks >= 0xFFFF) CHESS_THROW(CHESS_E_UNSUPPORTED, "row tile of %lld blocks is too long", (long long)blocks);
+        // u list
+        merged.assign(A->ci.begin() + A->rp[row0], A->ci.begin() + A->rp[r]);
+        std::sort(merged.begin(), merged.end());
+        merged.erase(std::unique(merged.begin(), merged.end()), merged.end());
+        const size_t ubase = u_cols.size();
+        u_cols.insert(u_cols.end(), merged.begin(), merged.end());
+        u_pos.resize(u_cols.size() * cmax, 0xFFFF);
+        max_u = std::max<int>(max_u, (int)merged.size());
+        for (int i = 0; i < c; ++i) {
+            const int row = row0 + i;
+            size_t k = 0;
+            for (int64_t q = A->rp[row]; q < A->rp[row + 1]; ++q) {
+                while (merged[k] < A->ci[q]) ++k;
+                u_pos[(ubase + k) * cmax + i] = (uint16_t)(q - A->rp[row0]);
+            }
+        }
+        u_off.push_back((int64_t)u_cols.size());
+        // j list
+        merged.assign(C->ci.begin() + C->rp[row0], C->ci.begin() + C->rp[r]);
+        std::sort(merged.begin(), merged.end());
+        merged.erase(std::unique(merged.begin(), merged.end()), merged.end());
+        const size_t jbase = j_cols.size();
+        j_cols.insert(j_cols.end(), merged.begin(), merged.end());
+        j_pos.resize(j_cols.size() * cmax, 0xFFFF);
+        for (int i = 0; i < c; ++i) {
+            const int row = row0 + i;
+            size_t k = 0;
+            for (int64_t q = C->rp[row]; q < C->rp[row + 1]; ++q) {
+                while (merged[k] < C->ci[q]) ++k;
+                if (q - C->rp[row] >= 0xFFFF) CHESS_THROW(CHESS_E_UNSUPPORTED, "output row too long");
+                j_pos[(jbase + k) * cmax + i] = (uint16_t)(q - C->rp[row]);
+            }
+        }
+        j_off.push_back((int64_t)j_cols.size());
+    }
+    tile_row0.push_back(A->nb);
+    if (max_u >= 32767) CHESS_THROW(CHESS_E_UNSUPPORTED, "row tile with %d distinct columns", max_u);
+    int hl = 1;
+    while ((1 << hl) < 2 * max_u) ++hl;
+    hipStream_t st = ctx->stream;
+    upload(P->d_tile_row0, tile_row0, st);
+    upload(P->d_u_off, u_off, st);
+    upload(P->d_u_cols, u_cols, st);
+    upload(P->d_u_pos, u_pos, st);
+    upload(P->d_j_off, j_off, st);
+    upload(P->d_j_cols, j_cols, st);
+    upload(P->d_j_pos, j_pos, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    ProductPlanDev &d = P->dev;
+    d.ntiles = (int)tile_row0.size() - 1;
+    d.cmax = cmax;
+    d.hcap_log2 = hl;
+    d.lds_ablocks = lds_ablocks;
+    d.max_u = max_u;
+    d.tile_row0 = P->d_tile_row0.as<int32_t>();
+    d.u_off = P->d_u_off.as<int64_t>();
+    d.u_cols = P->d_u_cols.as<int32_t>();
+    d.u_pos = P->d_u_pos.as<uint16_t>();
+    d.j_off = P->d_j_off.as<int64_t>();
+    d.j_cols = P->d_j_cols.as<int32_t>();
+    d.j_pos = P->d_j_pos.as<uint16_t>();
+    const size_t lds = masked_product_lds_bytes(dtype, b, d);
+    if (lds > 160 * 1024) CHESS_THROW(CHESS_E_UNSUPPORTED, "product tile needs %zu bytes of LDS", lds);
+    ctx->plans.push_back(std::move(P));
+    return ctx->plans.back().get();
+}
+
+// C = P_C o (A Bt^T) with an epilogue.  A, Bt, C value arrays in dtype.
+static void product(chess_ctx *ctx, int dtype, const ProductPlan *plan, const void *a,
+                    const void *bt, void *c, const Epilogue &ep) {
+    ProductOperands ops;
+    ops.a_rp = plan->a->d_rp.as<int64_t>();
+    ops.a_val = a;
+    ops.bt_rp = plan->bt->d_rp.as<int64_t>();
+    ops.bt_ci = plan->bt->d_ci.as<int32_t>();
+    ops.bt_val = bt;
+    ops.c_rp = plan->c->d_rp.as<int64_t>();
+    ops.c_out = c;
+    HIPCHECK(launch_masked_product(dtype, plan->a->b, plan->dev, ops, ep, ctx->stream));
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+static size_t vbytes(const Pattern *P, int dtype) {
+    return (size_t)P->nnzb * P->b * P->b * (dtype == 1 ? 4 : 8);
+}
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st;
+    explicit Timer(hipStream_t s) : st(s) {
+        HIPCHECK(hipEventCreate(&a));
+        HIPCHECK(hipEventCreate(&b));
+    }
+    ~Timer() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+    void start() { HIPCHECK(hipEventRecord(a, st)); }
+    double stop() {
+        HIPCHECK(hipEventRecord(b, st));
+        HIPCHECK(hipEventSynchronize(b));
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+};
+
+// Gershgorin bounds of a float64 matrix on pattern P.
+static void gershgorin(chess_ctx *ctx, const Pattern *P, const double *val, double *lo, double *hi) {
+    const int nparts = 256;
+    DevBuf part(sizeof(double) * (2 * nparts + 2));
+    double *plo = part.as<double>(), *phi = plo + nparts, *out = phi + nparts;
+    HIPCHECK(launch_gershgorin(P->b, P->nb, P->d_rp.as<int64_t>(), P->d_ci.as<int32_t>(), val, plo, phi, nparts, ctx->stream));
+    HIPCHECK(launch_minmax(nparts, plo, phi, out, ctx->stream));
+    double h[2];
+    HIPCHECK(hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    *lo = h[0];
+    *hi = h[1];
+}
+
+// k steps of Lanczos with full reorthogonalisation on a float64 matrix;
+// returns the extreme Ritz values and their residual norms.
+static void lanczos(chess_ctx *ctx, const Pattern *P, const double *val, int k, double *tmin,
+                    double *tmax, double *rmin, double *rmax) {
+    const int64_t n = P->n();
+    k = (int)std::min<int64_t>(k, n);
+    hipStream_t st = ctx->stream;
+    DevBuf V(sizeof(double) * (size_t)(k + 1) * n), w(sizeof(double) * n);
+    const int nparts = 128;
+    DevBuf part(sizeof(double) * (size_t)(k + 1) * nparts), h(sizeof(double) * (k + 2));
+    // seeded start vector (xorshift64*, normalised on the device)
+    std::vector<double> v0(n);
+    uint64_t s = 0x9E3779B97F4A7C15ull;
+    for (int64_t i = 0; i < n; ++i) {
+        s ^= s >> 12;
+        s ^= s << 25;
+        s ^= s >> 27;
+        v0[i] = (double)((s * 2685821657736338717ull) >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+    HIPCHECK(hipMemcpyAsync(w.p, v0.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    double *Vd = V.as<double>(), *wd = w.as<double>(), *hd = h.as<double>(), *pd = part.as<double>();
+    HIPCHECK(launch_multidot(1, n, wd, wd, pd, nparts, st));
+    HIPCHECK(launch_reduce_rows(1, nparts, pd, hd + k + 1, st));
+    HIPCHECK(launch_normalize(n, wd, hd + k + 1, Vd, st));
+    std::vector<double> alpha, beta;
+    double beta_last = 0.0;
+    for (int j = 0; j < k; ++j) {
+        double *vj = Vd + (size_t)j * n;
+        HIPCHECK(launch_spmv(P->b, P->nb, P->d_rp.as<int64_t>(), P->d_ci.as<int32_t>(), val, vj, wd, st));
+        for (int pass = 0; pass < 2; ++pass) {
+            HIPCHECK(launch_multidot(j + 1, n, Vd, wd, pd, nparts, st));
+            HIPCHECK(launch_reduce_rows(j + 1, nparts, pd, hd, st));
+            if (pass == 0) {
+                double aj;
+                HIPCHECK(hipMemcpyAsync(&aj, hd + j, sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPCHECK(hipStreamSynchronize(st));
+                alpha.push_back(aj);
+            }
+            HIPCHECK(launch_multiaxpy(j + 1, n, Vd, hd, wd, st));
+        }
+        HIPCHECK(launch_multidot(1, n, wd, wd, pd, nparts, st));
+        HIPCHECK(launch_reduce_rows(1, nparts, pd, hd + k + 1, st));
+        double nrm2;
+        HIPCHECK(hipMemcpyAsync(&nrm2, hd + k + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        const double bj = std::sqrt(std::max(nrm2, 0.0));
+        beta_last = bj;
+        if (j + 1 == k || bj < 1e-12) break;
+        beta.push_back(bj);
+        HIPCHECK(launch_normalize(n, wd, hd + k + 1, Vd + (size_t)(j + 1) * n, st));
+    }
+    beta.resize(alpha.size() > 0 ? alpha.size() - 1 : 0);
+    hostmath::tridiag_extremes(alpha, beta, beta_last, tmin, tmax, rmin, rmax);
+}
+
+// ---------------------------------------------------------------------------
+// the Chebyshev chain
+// ---------------------------------------------------------------------------
+
+struct ChainRequest {
+    const Pattern *PM = nullptr;  // pattern of M~
+    const double *Mt = nullptr;   // M~ (float64) on PM
+    const Pattern *PK = nullptr;  // pattern of the T_k
+    int n_pl = 0;
+    int nq = 0;
+    const double *coef = nullptr;  // host [nq][n_pl]
+    double *acc[4] = {nullptr, nullptr, nullptr, nullptr};  // device, float64 on PK (transposed storage)
+    int dtype = 0;
+    void *hist = nullptr;  // optional device [n_pl][nnzK*b*b] in dtype
+    std::vector<double> *moments = nullptr;
+    double kernel_ms = 0.0;  // out: device time of the product launches
+};
+
+// Runs T_0 .. T_{n_pl-1} in transposed storage U_k = T_k^T (see kernels.hip).
+static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
+    hipStream_t st = ctx->stream;
+    const Pattern *PM = rq.PM, *PK = rq.PK;
+    const int b = PK->b;
+    const int dtype = rq.dtype;
+    const int64_t nK = PK->nnzb * b * b;
+    const EmbedMap *emb = get_embed(ctx, PM, PK, "M~ in the chain pattern");
+    const ProductPlan *plan = get_plan(ctx, PK, PM, PK, dtype);
+    const size_t tb = vbytes(PK, dtype);
+    DevBuf U0(tb), U1(tb), Bt(vbytes(PM, dtype));
+    // Bt = M~^T on PM (row j of Bt = column j of M~)
+    HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, PM->d_tmap.as<int64_t>(), rq.Mt, Bt.p, 1, st));
+    // U_0 = I, U_1 = M~^T placed in PK
+    HIPCHECK(launch_fill_identity(dtype, b, PK->nnzb, PK->d_brow.as<int32_t>(), PK->d_ci.as<int32_t>(), U0.p, st));
+    HIPCHECK(launch_zero(U1.p, tb, st));
+    if (rq.n_pl > 1)
+        HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, emb->d_map_t.as<int64_t>(), rq.Mt, U1.p, 1, st));
+    for (int q = 0; q < rq.nq; ++q) {
+        const double *c = rq.coef + (size_t)q * rq.n_pl;
+        HIPCHECK(launch_axpby_to_f64(dtype, nK, 0.5 * c[0], U0.p, rq.n_pl > 1 ? c[1] : 0.0, U1.p, rq.acc[q], st));
+    }
+    if (rq.hist) {
+        HIPCHECK(hipMemcpyAsync(rq.hist, U0.p, tb, hipMemcpyDeviceToDevice, st));
+        if (rq.n_pl > 1)
+            HIPCHECK(hipMemcpyAsync((char *)rq.hist + tb, U1.p, tb, hipMemcpyDeviceToDevice, st));
+    }
+    const int ntiles = plan->dev.ntiles;
+    const int nsteps = std::max(rq.n_pl, 2);
+    DevBuf part(sizeof(double) * (size_t)nsteps * std::max(ntiles, 256));
+    DevBuf mom(sizeof(double) * nsteps);
+    double *pd = part.as<double>();
+    const int tparts = 256;
+    // moments 0 and 1
+    HIPCHECK(launch_trace(dtype, b, PK->nb, PK->d_diag.as<int64_t>(), U0.p, pd, tparts, st));
+    HIPCHECK(launch_reduce_rows(1, tparts, pd, mom.as<double>(), st));
+    if (rq.n_pl > 1) {
+        HIPCHECK(launch_trace(dtype, b, PK->nb, PK->d_diag.as<int64_t>(), U1.p, pd + tparts, tparts, st));
+        HIPCHECK(launch_reduce_rows(1, tparts, pd + tparts, mom.as<double>() + 1, st));
+    }
+    void *ucur = U1.p, *uprev = U0.p;
+    Timer tm(st);
+    tm.start();
+    for (int k = 1; k + 1 < rq.n_pl; ++k) {
+        Epilogue ep;
+        ep.alpha = 2.0;
+        ep.beta = -1.0;
+        ep.prev = uprev;
+        ep.nacc = rq.nq;
+        for (int q = 0; q < rq.nq; ++q) {
+            ep.acc[q] = rq.acc[q];
+            ep.coef[q] = rq.coef[(size_t)q * rq.n_pl + k + 1];
+        }
+        ep.hist = rq.hist ? (char *)rq.hist + (size_t)(k + 1) * tb : nullptr;
+        ep.trace_partial = pd + (size_t)(k + 1) * ntiles;
+        product(ctx, dtype, plan, ucur, Bt.p, uprev, ep);
+        std::swap(ucur, uprev);
+    }
+    rq.kernel_ms = tm.stop();
+    if (rq.n_pl > 2)
+        HIPCHECK(launch_reduce_rows(rq.n_pl - 2, ntiles, pd + 2 * (size_t)ntiles, mom.as<double>() + 2, st));
+    if (rq.moments) {
+        rq.moments->assign(rq.n_pl, 0.0);
+        HIPCHECK(hipMemcpyAsync(rq.moments->data(), mom.p, sizeof(double) * rq.n_pl, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// option handling
+// ---------------------------------------------------------------------------
+
+static chess_opts resolve_opts(const chess_opts *o) {
+    chess_opts r;
+    chess_default_opts(&r);
+    if (o) r = *o;
+    if (r.precision != CHESS_F64 && r.precision != CHESS_F32) CHESS_THROW(CHESS_E_UNSUPPORTED, "precision %d", r.precision);
+    if (r.smearing != CHESS_ERFC && r.smearing != CHESS_FERMI_DIRAC) CHESS_THROW(CHESS_E_ARG, "smearing %d", r.smearing);
+    const double deftol = r.precision == CHESS_F64 ? 1e-10 : 1e-6;
+    if (!(r.tol_fit > 0)) r.tol_fit = deftol;
+    if (!(r.tol_fit_s > 0)) r.tol_fit_s = deftol;
+    if (r.max_reexpand < 0) r.max_reexpand = 0;
+    if (r.lanczos_steps <= 0) r.lanczos_steps = 40;
+    if (!(r.eig_width > 0)) r.eig_width = 1e-3;
+    if (!(r.bound_margin >= 0)) r.bound_margin = 0.02;
+    return r;
+}
+
+static void check_matrix(const chess_matrix *M, const char *what) {
+    if (!M) CHESS_THROW(CHESS_E_ARG, "%s: null matrix", what);
+    if (M->dtype != CHESS_F64) CHESS_THROW(CHESS_E_UNSUPPORTED, "%s: dtype must be CHESS_F64", what);
+    if (!M->val) CHESS_THROW(CHESS_E_ARG, "%s: null values", what);
+}
+
+// Bounds of S for x^a with a possibly non-integer / negative: Gershgorin
+// upper bound; Gershgorin lower bound when positive, else Lanczos.
+static void s_bounds(chess_ctx *ctx, const Pattern *PS, const double *S, const chess_opts &o,
+                     bool need_positive, double *lo, double *hi) {
+    if (std::isfinite(o.s_bounds[0]) && std::isfinite(o.s_bounds[1])) {
+        *lo = o.s_bounds[0];
+        *hi = o.s_bounds[1];
+    } else {
+        double glo, ghi;
+        gershgorin(ctx, PS, S, &glo, &ghi);
+        *hi = ghi;
+        *lo = glo;
+        if (need_positive && glo <= 0) {
+            double tmin, tmax, rmin, rmax;
+            lanczos(ctx, PS, S, o.lanczos_steps, &tmin, &tmax, &rmin, &rmax);
+            *lo = tmin - rmin - o.bound_margin * (tmax - tmin);
+        }
+    }
+    if (!(*hi > *lo)) CHESS_THROW(CHESS_E_ARG, "empty spectral interval [%g, %g]", *lo, *hi);
+    if (need_positive && !(*lo > 0)) CHESS_THROW(CHESS_E_NOT_SPD, "lower spectral bound %g is not positive", *lo);
+}
+
+// |t_k| <= n (1 + 1e-2) holds whenever the spectrum is inside the bounds.
+static bool growth_ok(const std::vector<double> &t, int64_t n) {
+    for (double v : t)
+        if (!std::isfinite(v) || std::fabs(v) > 1.01 * (double)n) return false;
+    return true;
+}
+
+// x^a by the chain on S~ (U-form accumulator -> acc, transposed storage).
+struct PowerResult {
+    double lo, hi;
+    int n_pl;
+    int reexp;
+    double kernel_ms;
+};
+
+static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *S,
+                               const Pattern *PK, const std::vector<double> &powers,
+                               const chess_opts &o, int n_pl_fixed, double tol, double *const *acc,
+                               double lo, double hi) {
+    hipStream_t st = ctx->stream;
+    DevBuf St(sizeof(double) * (size_t)PS->nnzb * PS->b * PS->b);
+    PowerResult r{lo, hi, 0, 0, 0.0};
+    for (int attempt = 0;; ++attempt) {
+        double sigma, tau;
+        hostmath::scale_shift(r.lo, r.hi, &sigma, &tau);
+        HIPCHECK(launch_scale_shift(PS->b, PS->nnzb, PS->d_brow.as<int32_t>(), PS->d_ci.as<int32_t>(), S, St.as<double>(), sigma, tau, st));
+        int n_pl = n_pl_fixed;
+        if (n_pl <= 0) {
+            n_pl = 1;
+            for (double a : powers) {
+                const int m = hostmath::degree([a](double x) { return std::pow(x, a); }, r.lo, r.hi, tol, 8, 20000, 2048);
+                if (m < 0) CHESS_THROW(CHESS_E_NOCONV, "no degree up to 20000 reaches tol_fit %g for x^%g", tol, a);
+                n_pl = std::max(n_pl, m);
+            }
+        }
+        std::vector<double> coef((size_t)powers.size() * n_pl);
+        for (size_t q = 0; q < powers.size(); ++q) {
+            const double a = powers[q];
+            auto c = hostmath::cheb_coeffs([a](double x) { return std::pow(x, a); }, r.lo, r.hi, n_pl);
+            std::copy(c.begin(), c.end(), coef.begin() + q * n_pl);
+        }
+        std::vector<double> mom;
+        ChainRequest rq;
+        rq.PM = PS;
+        rq.Mt = St.as<double>();
+        rq.PK = PK;
+        rq.n_pl = n_pl;
+        rq.nq = (int)powers.size();
+        rq.coef = coef.data();
+        for (size_t q = 0; q < powers.size(); ++q) rq.acc[q] = acc[q];
+        rq.dtype = o.precision;
+        rq.moments = &mom;
+        run_chain(ctx, rq);
+        r.n_pl = n_pl;
+        r.kernel_ms += rq.kernel_ms;
+        if (growth_ok(mom, PK->n())) break;
+        if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "spectral bounds [%g, %g] still fail the growth test", r.lo, r.hi);
+        // widen both sides by 10% of the width (the lower bound stays positive)
+        const double w = r.hi - r.lo;
+        r.hi += 0.1 * w;
+        r.lo = std::max(r.lo - 0.1 * w, 0.5 * r.lo);
+        r.reexp++;
+    }
+    return r;
+}
+
+static void transpose_into(chess_ctx *ctx, const Pattern *P, const double *in, double *out) {
+    HIPCHECK(launch_scatter_blocks(0, P->b, P->nnzb, P->d_tmap.as<int64_t>(), in, out, 1, ctx->stream));
+}
+
+static void require_same(const Pattern *a, const Pattern *b, const char *what) {
+    if (a != b) CHESS_THROW(CHESS_E_PATTERN, "%s: output must be allocated on exactly the given pattern", what);
+}
+
+static void set_err(chess_ctx *ctx, const Error &e) { ctx->err = e.msg; }
+
+// Orthogonal frame: X^T (accX, transposed storage), X, and H' on PH.
+struct Frame {
+    DevBuf accX, X, Hp;
+    PowerResult s;
+    double ms_s = 0, ms_transform = 0;
+};
+
+static void build_frame(chess_ctx *ctx, const Pattern *PH, const double *H, const Pattern *PS,
+                        const double *S, const Pattern *PK, const chess_opts &o, Frame &F) {
+    hipStream_t st = ctx->stream;
+    Timer t(st);
+    t.start();
+    double slo, shi;
+    s_bounds(ctx, PS, S, o, true, &slo, &shi);
+    F.accX.alloc(sizeof(double) * (size_t)PK->nnzb * PK->b * PK->b);
+    double *accs[1] = {F.accX.as<double>()};
+    F.s = power_chain(ctx, PS, S, PK, {-0.5}, o, o.n_pl_s, o.tol_fit_s, accs, slo, shi);
+    F.ms_s = t.stop();
+    t.start();
+    const EmbedMap *eh = get_embed(ctx, PH, PK, "H in the kernel pattern");
+    (void)eh;
+    // Z^T = P_K o (X^T H^T): A = X^T (= accX), Bt = H
+    DevBuf ZT(sizeof(double) * (size_t)PK->nnzb * PK->b * PK->b);
+    product(ctx, 0, get_plan(ctx, PK, PH, PK, 0), F.accX.p, H, ZT.p, Epilogue{});
+    // X = (accX)^T
+    F.X.alloc(ZT.bytes);
+    transpose_into(ctx, PK, F.accX.as<double>(), F.X.as<double>());
+    // H' = P_H o (X Z): A = X, Bt = Z^T; then symmetrise
+    DevBuf Hraw(sizeof(double) * (size_t)PH->nnzb * PH->b * PH->b);
+    product(ctx, 0, get_plan(ctx, PK, PK, PH, 0), F.X.p, ZT.p, Hraw.p, Epilogue{});
+    F.Hp.alloc(Hraw.bytes);
+    HIPCHECK(launch_symmetrize(PH->b, PH->nnzb, PH->d_tmap.as<int64_t>(), Hraw.as<double>(), F.Hp.as<double>(), st));
+    F.ms_transform = t.stop();
+}
+
+static void h_bounds(chess_ctx *ctx, const Pattern *PH, const double *Hp, const chess_opts &o,
+                     double *lo, double *hi) {
+    if (std::isfinite(o.bounds[0]) && std::isfinite(o.bounds[1])) {
+        *lo = o.bounds[0];
+        *hi = o.bounds[1];
+    } else if (o.bounds_mode == CHESS_BOUNDS_LANCZOS) {
+        double tmin, tmax, rmin, rmax;
+        lanczos(ctx, PH, Hp, o.lanczos_steps, &tmin, &tmax, &rmin, &rmax);
+        const double w = tmax - tmin;
+        *lo = tmin - rmin - o.bound_margin * w;
+        *hi = tmax + rmax + o.bound_margin * w;
+    } else {
+        gershgorin(ctx, PH, Hp, lo, hi);
+    }
+    if (!(*hi > *lo)) CHESS_THROW(CHESS_E_ARG, "empty spectral interval [%g, %g]", *lo, *hi);
+}
+
+static hostmath::Fn occupation(int smearing, double mu, double kT) {
+    if (smearing == CHESS_ERFC) return [mu, kT](double e) { return hostmath::occ_erfc(e, mu, kT); };
+    return [mu, kT](double e) { return hostmath::occ_fd(e, mu, kT); };
+}
+
+// K = P_K o (X P_K o (K' X)) from accK = K'^T; Tr(KS).
+static double post_transform(chess_ctx *ctx, const Pattern *PK, const Frame &F, const double *accK,
+                             const Pattern *PS, const double *S, double *Kout) {
+    const size_t bytes = sizeof(double) * (size_t)PK->nnzb * PK->b * PK->b;
+    DevBuf Kp(bytes), WT(bytes);
+    transpose_into(ctx, PK, accK, Kp.as<double>());
+    // W^T = P_K o (X^T K'^T): A = X^T (accX), Bt = K'
+    product(ctx, 0, get_plan(ctx, PK, PK, PK, 0), F.accX.p, Kp.p, WT.p, Epilogue{});
+    // K = P_K o (X W): A = X, Bt = W^T
+    product(ctx, 0, get_plan(ctx, PK, PK, PK, 0), F.X.p, WT.p, Kout, Epilogue{});
+    // Tr(K S) = sum over S blocks (J, I) of <K(I, J), S(J, I)^T>
+    const EmbedMap *es = get_embed(ctx, PS, PK, "S in the kernel pattern");
+    const int nparts = 256;
+    DevBuf part(sizeof(double) * (nparts + 1));
+    HIPCHECK(launch_trace_product(PK->b, PS->nnzb, es->d_map_t.as<int64_t>(), Kout, S, part.as<double>(), nparts, ctx->stream));
+    HIPCHECK(launch_reduce_rows(1, nparts, part.as<double>(), part.as<double>() + nparts, ctx->stream));
+    double tr;
+    HIPCHECK(hipMemcpyAsync(&tr, part.as<double>() + nparts, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    return tr;
+}
+
+static void fill_info_defaults(chess_info *info) {
+    if (!info) return;
+    std::memset(info, 0, sizeof(*info));
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    info->mu = info->lo = info->hi = info->s_lo = info->s_hi = nan;
+    info->tr_ks = info->ne_chain = info->penalty = nan;
+}
+
+static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
+                           const chess_pattern *pattern, double n_e, double kT,
+                           chess_matrix *K_out, chess_info *info, const chess_opts *opts) {
+    const double t_begin = now_ms();
+    chess_opts o = resolve_opts(opts);
+    check_matrix(H, "H");
+    check_matrix(S, "S");
+    check_matrix(K_out, "K_out");
+    if (!(kT > 0)) CHESS_THROW(CHESS_E_ARG, "kT must be positive");
+    const Pattern *PH = get_pattern(ctx, &H->pat, "H pattern");
+    const Pattern *PS = get_pattern(ctx, &S->pat, "S pattern");
+    const Pattern *PK = get_pattern(ctx, pattern, "kernel pattern");
+    require_same(get_pattern(ctx, &K_out->pat, "K_out pattern"), PK, "K_out");
+    if (PH->nb != PK->nb || PS->nb != PK->nb || PH->b != PK->b || PS->b != PK->b)
+        CHESS_THROW(CHESS_E_ARG, "H, S and the pattern differ in size or block edge");
+    const int64_t n = PK->n();
+    if (!(n_e >= 0 && n_e <= (double)n)) CHESS_THROW(CHESS_E_ARG, "n_electrons %g outside [0, %lld]", n_e, (long long)n);
+    get_embed(ctx, PH, PK, "H in the kernel pattern");
+    get_embed(ctx, PS, PK, "S in the kernel pattern");
+    hipStream_t st = ctx->stream;
+    const double t_setup = now_ms();
+
+    Frame F;
+    build_frame(ctx, PH, H->val ? (const double *)H->val : nullptr, PS, (const double *)S->val, PK, o, F);
+    const int b = PK->b;
+    const int dtype = o.precision;
+    const int64_t nK = PK->nnzb * b * b;
+    double lo, hi;
+    h_bounds(ctx, PH, F.Hp.as<double>(), o, &lo, &hi);
+
+    DevBuf Ht(sizeof(double) * (size_t)PH->nnzb * b * b);
+    DevBuf accK(sizeof(double) * (size_t)nK);
+    DevBuf hist;
+    std::vector<double> mom;
+    int n_pl = 0, reexp = 0, passes = 0;
+    double penalty = std::numeric_limits<double>::quiet_NaN();
+    double ms_chain = 0.0, kernel_ms = 0.0;
+    bool have_hist = false;
+    Timer tm(st);
+    for (int attempt = 0;; ++attempt) {
+        double sigma, tau;
+        hostmath::scale_shift(lo, hi, &sigma, &tau);
+        n_pl = o.n_pl;
+        if (n_pl <= 0) {
+            n_pl = hostmath::degree(occupation(o.smearing, tau, kT), lo, hi, o.tol_fit, 8, 20000, 2048);
+            if (n_pl < 0) CHESS_THROW(CHESS_E_NOCONV, "no degree up to 20000 reaches tol_fit %g", o.tol_fit);
+        }
+        HIPCHECK(launch_scale_shift(b, PH->nnzb, PH->d_brow.as<int32_t>(), PH->d_ci.as<int32_t>(), F.Hp.as<double>(), Ht.as<double>(), sigma, tau, st));
+        have_hist = false;
+        if (o.store_history && !std::isfinite(o.mu)) {
+            size_t freeb = 0, totalb = 0;
+            HIPCHECK(hipMemGetInfo(&freeb, &totalb));
+            const size_t need = vbytes(PK, dtype) * (size_t)n_pl;
+            if (need + ((size_t)1 << 30) < freeb) {
+                try {
+                    hist.alloc(need);
+                    have_hist = true;
+                } catch (const Error &) {
+                    have_hist = false;
+                }
+            }
+        }
+        tm.start();
+        ChainRequest rq;
+        rq.PM = PH;
+        rq.Mt = Ht.as<double>();
+        rq.PK = PK;
+        rq.n_pl = n_pl;
+        rq.dtype = dtype;
+        rq.moments = &mom;
+        std::vector<double> c_fixed;
+        if (std::isfinite(o.mu)) {
+            // mu given: one accumulating pass
+            c_fixed = hostmath::cheb_coeffs(occupation(o.smearing, o.mu, kT), lo, hi, n_pl);
+            rq.nq = 1;
+            rq.coef = c_fixed.data();
+            rq.acc[0] = accK.as<double>();
+        }
+        rq.hist = have_hist ? hist.p : nullptr;
+        run_chain(ctx, rq);
+        ms_chain += tm.stop();
+        kernel_ms += rq.kernel_ms;
+        passes++;
+        double fit_err = 1.0;
+        penalty = hostmath::penalty_trace(mom, -200.0, &fit_err);
+        const bool pen_valid = fit_err * (double)n < 0.1;
+        bool ok = growth_ok(mom, n);
+        if (pen_valid && std::fabs(penalty) > 0.5) ok = false;
+        if (!pen_valid) penalty = std::numeric_limits<double>::quiet_NaN();
+        if (ok) break;
+        if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "spectral bounds [%g, %g] still fail after %d widenings", lo, hi, attempt);
+        const double w = hi - lo;
+        // Eq. 6 sign tells which side: positive -> an eigenvalue below lo
+        if (pen_valid && penalty > 0.5)
+            lo -= 0.1 * w;
+        else if (pen_valid && penalty < -0.5)
+            hi += 0.1 * w;
+        else {
+            lo -= 0.1 * w;
+            hi += 0.1 * w;
+        }
+        reexp++;
+    }
+    // mu search on the moments
+    const double t_mu0 = now_ms();
+    double mu = o.mu;
+    int iters = 0;
+    hostmath::CountFunction N;
+    N.init(mom, lo, hi, kT, o.smearing == CHESS_ERFC ? 0 : 1);
+    if (!std::isfinite(mu)) {
+        const double tol_ne = o.tol_ne > 0 ? o.tol_ne : 1e-8 * n_e;
+        bool found = false;
+        if (std::isfinite(o.mu_bracket[0]) && std::isfinite(o.mu_bracket[1]))
+            found = hostmath::bisect_mu(N, n_e, tol_ne, o.mu_bracket[0], o.mu_bracket[1], &mu, &iters);
+        if (!found) {
+            int it2 = 0;
+            found = hostmath::bisect_mu(N, n_e, tol_ne, lo - 20 * kT, hi + 20 * kT, &mu, &it2);
+            iters += it2;
+        }
+        if (!found) CHESS_THROW(CHESS_E_NOCONV, "N(mu) does not bracket %g electrons", n_e);
+    }
+    const double ms_mu = now_ms() - t_mu0;
+    const std::vector<double> c = hostmath::cheb_coeffs(occupation(o.smearing, mu, kT), lo, hi, n_pl);
+    double ne_chain = 0.5 * c[0] * mom[0];
+    for (int j = 1; j < n_pl; ++j) ne_chain += c[j] * mom[j];
+    if (!std::isfinite(o.mu)) {
+        tm.start();
+        if (have_hist) {
+            DevBuf dc(sizeof(double) * n_pl);
+            std::vector<double> cc(c);
+            cc[0] *= 0.5;  // T_0 enters with c_0/2
+            HIPCHECK(hipMemcpyAsync(dc.p, cc.data(), sizeof(double) * n_pl, hipMemcpyHostToDevice, st));
+            HIPCHECK(launch_recombine(dtype, nK, n_pl, hist.p, dc.as<double>(), accK.as<double>(), st));
+            HIPCHECK(hipStreamSynchronize(st));
+        } else {
+            ChainRequest rq;
+            rq.PM = PH;
+            rq.Mt = Ht.as<double>();
+            rq.PK = PK;
+            rq.n_pl = n_pl;
+            rq.dtype = dtype;
+            rq.nq = 1;
+            rq.coef = c.data();
+            rq.acc[0] = accK.as<double>();
+            run_chain(ctx, rq);
+            kernel_ms += rq.kernel_ms;
+            passes++;
+        }
+        ms_chain += tm.stop();
+    }
+    hist.release();
+    Ht.release();
+    const double t_post0 = now_ms();
+    const double trks = post_transform(ctx, PK, F, accK.as<double>(), PS, (const double *)S->val, (double *)K_out->val);
+    const double t_end = now_ms();
+    if (info) {
+        info->mu = mu;
+        info->lo = lo;
+        info->hi = hi;
+        info->s_lo = F.s.lo;
+        info->s_hi = F.s.hi;
+        info->tr_ks = trks;
+        info->ne_chain = ne_chain;
+        info->penalty = penalty;
+        info->n_pl = n_pl;
+        info->n_pl_s = F.s.n_pl;
+        info->passes = passes;
+        info->bisect_iters = iters;
+        info->reexpansions = reexp + F.s.reexp;
+        info->chain_steps = passes * std::max(n_pl - 2, 0) + std::max(F.s.n_pl - 2, 0);
+        info->ms_total = t_end - t_begin;
+        info->ms_setup = t_setup - t_begin;
+        info->ms_s_chain = F.ms_s;
+        info->ms_transform = F.ms_transform;
+        info->ms_h_chain = ms_chain;
+        info->ms_mu = ms_mu;
+        info->ms_post = t_end - t_post0;
+        info->ms_chain_kernel = kernel_ms;
+    }
+}
+
+static void matrix_power(chess_ctx *ctx, const chess_matrix *S, double a,
+                         const chess_pattern *pattern, chess_matrix *out, chess_info *info,
+                         const chess_opts *opts) {
+    const double t0 = now_ms();
+    chess_opts o = resolve_opts(opts);
+    check_matrix(S, "S");
+    check_matrix(out, "Sa_out");
+    if (!std::isfinite(a)) CHESS_THROW(CHESS_E_ARG, "power must be finite");
+    const Pattern *PS = get_pattern(ctx, &S->pat, "S pattern");
+    const Pattern *PK = get_pattern(ctx, pattern, "output pattern");
+    require_same(get_pattern(ctx, &out->pat, "Sa_out pattern"), PK, "Sa_out");
+    get_embed(ctx, PS, PK, "S in the output pattern");
+    const bool need_pos = !(a == std::floor(a) && a >= 0);
+    double lo, hi;
+    s_bounds(ctx, PS, (const double *)S->val, o, need_pos, &lo, &hi);
+    if (o.n_pl > 0) o.n_pl_s = o.n_pl;
+    DevBuf acc(sizeof(double) * (size_t)PK->nnzb * PK->b * PK->b);
+    double *accs[1] = {acc.as<double>()};
+    PowerResult r = power_chain(ctx, PS, (const double *)S->val, PK, {a}, o, o.n_pl_s, o.tol_fit_s, accs, lo, hi);
+    transpose_into(ctx, PK, acc.as<double>(), (double *)out->val);
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    if (info) {
+        info->s_lo = info->lo = r.lo;
+        info->s_hi = info->hi = r.hi;
+        info->n_pl = info->n_pl_s = r.n_pl;
+        info->passes = 1;
+        info->reexpansions = r.reexp;
+        info->chain_steps = std::max(r.n_pl - 2, 0);
+        info->ms_total = now_ms() - t0;
+        info->ms_chain_kernel = r.kernel_ms;
+    }
+}
+
+static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
+                             double e_lo, double e_hi, const chess_pattern *pattern,
+                             double *eig_out, int64_t capacity, int64_t *n_found,
+                             chess_info *info, const chess_opts *opts) {
+    const double t0 = now_ms();
+    chess_opts o = resolve_opts(opts);
+    check_matrix(H, "H");
+    check_matrix(S, "S");
+    if (!n_found) CHESS_THROW(CHESS_E_ARG, "n_found is null");
+    if (capacity > 0 && !eig_out) CHESS_THROW(CHESS_E_ARG, "eig_out is null");
+    if (!(e_hi > e_lo)) CHESS_THROW(CHESS_E_ARG, "empty interval");
+    const Pattern *PH = get_pattern(ctx, &H->pat, "H pattern");
+    const Pattern *PS = get_pattern(ctx, &S->pat, "S pattern");
+    const Pattern *PK = get_pattern(ctx, pattern, "chain pattern");
+    get_embed(ctx, PH, PK, "H in the chain pattern");
+    get_embed(ctx, PS, PK, "S in the chain pattern");
+    Frame F;
+    build_frame(ctx, PH, (const double *)H->val, PS, (const double *)S->val, PK, o, F);
+    double lo, hi;
+    h_bounds(ctx, PH, F.Hp.as<double>(), o, &lo, &hi);
+    const int b = PK->b;
+    DevBuf Ht(sizeof(double) * (size_t)PH->nnzb * b * b);
+    std::vector<double> mom;
+    int n_pl = 0, reexp = 0;
+    double kernel_ms = 0;
+    for (int attempt = 0;; ++attempt) {
+        double sigma, tau;
+        hostmath::scale_shift(lo, hi, &sigma, &tau);
+        n_pl = o.n_pl;
+        if (n_pl <= 0) {
+            n_pl = hostmath::degree(occupation(CHESS_ERFC, tau, o.eig_width), lo, hi, o.tol_fit, 8, 20000, 2048);
+            if (n_pl < 0) CHESS_THROW(CHESS_E_NOCONV, "no degree up to 20000 reaches tol_fit %g", o.tol_fit);
+        }
+        HIPCHECK(launch_scale_shift(b, PH->nnzb, PH->d_brow.as<int32_t>(), PH->d_ci.as<int32_t>(), F.Hp.as<double>(), Ht.as<double>(), sigma, tau, ctx->stream));
+        ChainRequest rq;
+        rq.PM = PH;
+        rq.Mt = Ht.as<double>();
+        rq.PK = PK;
+        rq.n_pl = n_pl;
+        rq.dtype = o.precision;
+        rq.moments = &mom;
+        run_chain(ctx, rq);
+        kernel_ms += rq.kernel_ms;
+        if (growth_ok(mom, PK->n())) break;
+        if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "bounds [%g, %g] fail the growth test", lo, hi);
+        const double w = hi - lo;
+        lo -= 0.1 * w;
+        hi += 0.1 * w;
+        reexp++;
+    }
+    hostmath::CountFunction N;
+    N.init(mom, lo, hi, o.eig_width, 0);
+    std::vector<double> ev = hostmath::eigenvalues(N, e_lo, e_hi, 1e-10);
+    *n_found = (int64_t)ev.size();
+    if ((int64_t)ev.size() > capacity)
+        CHESS_THROW(CHESS_E_CAPACITY, "%lld eigenvalues in the interval, capacity %lld", (long long)ev.size(), (long long)capacity);
+    std::copy(ev.begin(), ev.end(), eig_out);
+    if (info) {
+        info->lo = lo;
+        info->hi = hi;
+        info->s_lo = F.s.lo;
+        info->s_hi = F.s.hi;
+        info->n_pl = n_pl;
+        info->n_pl_s = F.s.n_pl;
+        info->passes = 1 + reexp;
+        info->reexpansions = reexp;
+        info->ms_total = now_ms() - t0;
+        info->ms_chain_kernel = kernel_ms;
+    }
+}
+
+static void chebyshev(chess_ctx *ctx, const chess_matrix *M, double lo, double hi,
+                      const chess_pattern *pattern, int32_t n_pl, int32_t nq, const double *coef,
+                      chess_matrix *acc_out, double *moments, const chess_opts *opts) {
+    chess_opts o = resolve_opts(opts);
+    check_matrix(M, "M");
+    if (n_pl < 1) CHESS_THROW(CHESS_E_ARG, "n_pl must be >= 1");
+    if (nq < 0 || nq > 4) CHESS_THROW(CHESS_E_ARG, "nq must be in 0..4");
+    if (nq > 0 && (!coef || !acc_out)) CHESS_THROW(CHESS_E_ARG, "coefficients or outputs missing");
+    if (!(hi > lo)) CHESS_THROW(CHESS_E_ARG, "empty interval");
+    const Pattern *PM = get_pattern(ctx, &M->pat, "M pattern");
+    const Pattern *PK = get_pattern(ctx, pattern, "chain pattern");
+    if (PM->nb != PK->nb || PM->b != PK->b) CHESS_THROW(CHESS_E_ARG, "M and the pattern differ in size");
+    for (int q = 0; q < nq; ++q) {
+        check_matrix(&acc_out[q], "acc_out");
+        require_same(get_pattern(ctx, &acc_out[q].pat, "acc_out pattern"), PK, "acc_out");
+    }
+    get_embed(ctx, PM, PK, "M in the chain pattern");
+    hipStream_t st = ctx->stream;
+    const int b = PK->b;
+    DevBuf Mt(sizeof(double) * (size_t)PM->nnzb * b * b);
+    double sigma, tau;
+    hostmath::scale_shift(lo, hi, &sigma, &tau);
+    HIPCHECK(launch_scale_shift(b, PM->nnzb, PM->d_brow.as<int32_t>(), PM->d_ci.as<int32_t>(), (const double *)M->val, Mt.as<double>(), sigma, tau, st));
+    std::vector<std::unique_ptr<DevBuf>> accs;
+    ChainRequest rq;
+    rq.PM = PM;
+    rq.Mt = Mt.as<double>();
+    rq.PK = PK;
+    rq.n_pl = n_pl;
+    rq.nq = nq;
+    rq.coef = coef;
+    rq.dtype = o.precision;
+    for (int q = 0; q < nq; ++q) {
+        accs.push_back(std::make_unique<DevBuf>(sizeof(double) * (size_t)PK->nnzb * b * b));
+        rq.acc[q] = accs.back()->as<double>();
+    }
+    std::vector<double> mom;
+    rq.moments = &mom;
+    run_chain(ctx, rq);
+    for (int q = 0; q < nq; ++q) transpose_into(ctx, PK, rq.acc[q], (double *)acc_out[q].val);
+    HIPCHECK(hipStreamSynchronize(st));
+    if (moments) std::copy(mom.begin(), mom.end(), moments);
+}
+
+static void masked_product_api(chess_ctx *ctx, const chess_matrix *A, const chess_matrix *B,
+                               chess_matrix *C) {
+    check_matrix(A, "A");
+    check_matrix(B, "B");
+    check_matrix(C, "C");
+    const Pattern *PA = get_pattern(ctx, &A->pat, "A pattern");
+    const Pattern *PB = get_pattern(ctx, &B->pat, "B pattern");
+    const Pattern *PC = get_pattern(ctx, &C->pat, "C pattern");
+    if (PA->nb != PB->nb || PA->nb != PC->nb || PA->b != PB->b || PA->b != PC->b)
+        CHESS_THROW(CHESS_E_ARG, "A, B, C differ in size or block edge");
+    DevBuf BT(sizeof(double) * (size_t)PB->nnzb * PB->b * PB->b);
+    transpose_into(ctx, PB, (const double *)B->val, BT.as<double>());
+    product(ctx, 0, get_plan(ctx, PA, PB, PC, 0), A->val, BT.p, C->val, Epilogue{});
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+}
+
+template <typename F>
+static int guarded(chess_ctx *ctx, F &&f) {
+    if (!ctx) return CHESS_E_ARG;
+    try {
+        HIPCHECK(hipSetDevice(ctx->device));
+        f();
+        ctx->err = "no error";
+        return CHESS_OK;
+    } catch (const Error &e) {
+        set_err(ctx, e);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return CHESS_E_OOM;
+    } catch (...) {
+        ctx->err = "unexpected exception";
+        return CHESS_E_HIP;
+    }
+}
+
+}  // namespace chess
+
+extern "C" {
+
+void chess_default_opts(chess_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    o->precision = CHESS_F32;
+    o->smearing = CHESS_ERFC;
+    o->bounds_mode = CHESS_BOUNDS_GERSHGORIN;
+    o->n_pl = 0;
+    o->n_pl_s = 0;
+    o->store_history = 0;
+    o->max_reexpand = 3;
+    o->lanczos_steps = 40;
+    o->tol_fit = 0;
+    o->tol_fit_s = 0;
+    o->tol_ne = 0;
+    o->bounds[0] = o->bounds[1] = nan;
+    o->s_bounds[0] = o->s_bounds[1] = nan;
+    o->mu = nan;
+    o->mu_bracket[0] = o->mu_bracket[1] = nan;
+    o->eig_width = 1e-3;
+    o->bound_margin = 0.02;
+}
+
+int chess_create(chess_ctx **out, int device, void *stream) {
+    if (!out) return CHESS_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CHESS_E_HIP;
+    if (hipSetDevice(device) != hipSuccess) return CHESS_E_HIP;
+    chess_ctx *c = new (std::nothrow) chess_ctx();
+    if (!c) return CHESS_E_OOM;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return CHESS_OK;
+}
+
+int chess_destroy(chess_ctx *ctx) {
+    if (!ctx) return CHESS_E_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+    return CHESS_OK;
+}
+
+const char *chess_last_error(const chess_ctx *ctx) {
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+int chess_fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
+                         const chess_pattern *pattern, double n_electrons, double kT,
+                         chess_matrix *K_out, chess_info *info, const chess_opts *opts) {
+    chess::fill_info_defaults(info);
+    return chess::guarded(ctx, [&] { chess::fermi_operator(ctx, H, S, pattern, n_electrons, kT, K_out, info, opts); });
+}
+
+int chess_matrix_power(chess_ctx *ctx, const chess_matrix *S, double a,
+                       const chess_pattern *pattern, chess_matrix *Sa_out, chess_info *info,
+                       const chess_opts *opts) {
+    chess::fill_info_defaults(info);
+    return chess::guarded(ctx, [&] { chess::matrix_power(ctx, S, a, pattern, Sa_out, info, opts); });
+}
+
+int chess_eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
+                           double lo, double hi, const chess_pattern *pattern, double *eig_out,
+                           int64_t capacity, int64_t *n_found, chess_info *info,
+                           const chess_opts *opts) {
+    chess::fill_info_defaults(info);
+    return chess::guarded(ctx, [&] {
+        chess::eigs_in_interval(ctx, H, S, lo, hi, pattern, eig_out, capacity, n_found, info, opts);
+    });
+}
+
+int chess_chebyshev(chess_ctx *ctx, const chess_matrix *M, double lo, double hi,
+                    const chess_pattern *pattern, int32_t n_pl, int32_t nq, const double *coef,
+                    chess_matrix *acc_out, double *moments, const chess_opts *opts) {
+    return chess::guarded(ctx, [&] { chess::chebyshev(ctx, M, lo, hi, pattern, n_pl, nq, coef, acc_out, moments, opts); });
+}
+
+int chess_masked_product(chess_ctx *ctx, const chess_matrix *A, const chess_matrix *B,
+                         chess_matrix *C) {
+    return chess::guarded(ctx, [&] { chess::masked_product_api(ctx, A, B, C); });
+}
+
+}  // extern "C"

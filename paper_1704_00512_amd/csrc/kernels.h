@@ -1,0 +1,117 @@
+// Internal interface between the host pipeline (chess.cpp) and the HIP
+// kernels (kernels.hip).  Not part of the public C interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chess {
+
+// Symbolic plan of one masked block product C = P_C o (A Bt^T), all three in
+// block CSR.  Output block rows are grouped into tiles of consecutive rows;
+// a tile's rows of A are staged in LDS.  For every tile:
+//   u list: the distinct column indices of A over the tile's rows (sorted),
+//           with, per tile row i, the block's position inside the staged A
+//           tile (0xFFFF if row i has no such column);
+//   j list: the distinct column indices of C over the tile's rows (sorted),
+//           with, per tile row i, the block's offset inside C's row (0xFFFF
+//           if absent).
+struct ProductPlanDev {
+    int ntiles = 0;
+    int cmax = 0;          // rows per tile upper bound (kernel template value)
+    int hcap_log2 = 0;     // LDS hash table size = 1 << hcap_log2
+    int lds_ablocks = 0;   // largest A tile in blocks
+    int max_u = 0;         // largest u list
+    const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
+    const int64_t *u_off = nullptr;      // [ntiles + 1]
+    const int32_t *u_cols = nullptr;
+    const uint16_t *u_pos = nullptr;     // [total_u * cmax]
+    const int64_t *j_off = nullptr;      // [ntiles + 1]
+    const int32_t *j_cols = nullptr;
+    const uint16_t *j_pos = nullptr;     // [total_j * cmax]
+};
+
+// Epilogue applied to Y = P_C o (A Bt^T) at every output element:
+//   out = alpha * Y + beta * prev          (prev may be null: beta ignored)
+//   out is stored to `out` (may alias prev: each element is read then written
+//   by the same thread);
+//   acc[q] += coef[q] * out in float64 for q < nacc;
+//   hist (if set) receives a copy of out;
+//   trace_partial (if set) receives, per tile, the float64 sum of out over
+//   the diagonal elements of diagonal blocks.
+struct Epilogue {
+    double alpha = 1.0, beta = 0.0;
+    const void *prev = nullptr;
+    int nacc = 0;
+    double *acc[4] = {nullptr, nullptr, nullptr, nullptr};
+    double coef[4] = {0, 0, 0, 0};
+    void *hist = nullptr;
+    double *trace_partial = nullptr;
+};
+
+struct ProductOperands {
+    const int64_t *a_rp;
+    const void *a_val;
+    const int64_t *bt_rp;
+    const int32_t *bt_ci;
+    const void *bt_val;
+    const int64_t *c_rp;
+    void *c_out;
+};
+
+// dtype: 0 = double, 1 = float.  Returns a hipError_t.
+hipError_t launch_masked_product(int dtype, int b, const ProductPlanDev &plan,
+                                 const ProductOperands &ops, const Epilogue &ep,
+                                 hipStream_t st);
+size_t masked_product_lds_bytes(int dtype, int b, const ProductPlanDev &plan);
+
+// Elementwise and small kernels (all on block-CSR value arrays, nb = blocks).
+hipError_t launch_fill_identity(int dtype, int b, int64_t nnzb, const int32_t *brow,
+                                const int32_t *bcol, void *out, hipStream_t st);
+// out[map[p]] = transpose_if(in[p]) (converted to dtype_out); out must be zeroed
+// first when the map does not cover it.
+hipError_t launch_scatter_blocks(int dtype_out, int b, int64_t nnzb_in, const int64_t *map,
+                                 const double *in, void *out, int transpose, hipStream_t st);
+// out = sigma * (in - tau I) (float64, same pattern)
+hipError_t launch_scale_shift(int b, int64_t nnzb, const int32_t *brow, const int32_t *bcol,
+                              const double *in, double *out, double sigma, double tau,
+                              hipStream_t st);
+// out[p] = 0.5 (in[p] + in[tmap[p]]^T)
+hipError_t launch_symmetrize(int b, int64_t nnzb, const int64_t *tmap, const double *in,
+                             double *out, hipStream_t st);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+// acc = a0 * T0 + a1 * T1 (T in dtype, acc float64)
+hipError_t launch_axpby_to_f64(int dtype, int64_t n, double a0, const void *t0, double a1,
+                               const void *t1, double *acc, hipStream_t st);
+// acc[x] = sum_k coef[k] hist[k][x] for k < nk (coef on device)
+hipError_t launch_recombine(int dtype, int64_t n, int nk, const void *hist, const double *coef,
+                            double *acc, hipStream_t st);
+// Per block row diagonal trace partials, reduced per tile of rows.
+hipError_t launch_trace(int dtype, int b, int nb, const int64_t *diag_idx, const void *val,
+                        double *out_partial, int nparts, hipStream_t st);
+// out[s] = sum_t part[s * nparts + t], fixed order.
+hipError_t launch_reduce_rows(int nrows, int nparts, const double *part, double *out,
+                              hipStream_t st);
+// Gershgorin: per scalar row d - R and d + R, reduced to per-tile min/max.
+hipError_t launch_gershgorin(int b, int nb, const int64_t *rp, const int32_t *ci,
+                             const double *val, double *part_lo, double *part_hi, int nparts,
+                             hipStream_t st);
+hipError_t launch_minmax(int nparts, const double *part_lo, const double *part_hi, double *out2,
+                         hipStream_t st);
+// y = A x (block CSR, float64)
+hipError_t launch_spmv(int b, int nb, const int64_t *rp, const int32_t *ci, const double *val,
+                       const double *x, double *y, hipStream_t st);
+// h[j] = V[j] . w for j < m (V row-major [m][n]) ; partials per tile
+hipError_t launch_multidot(int m, int64_t n, const double *V, const double *w, double *part,
+                           int nparts, hipStream_t st);
+// w -= sum_j h[j] V[j]
+hipError_t launch_multiaxpy(int m, int64_t n, const double *V, const double *h, double *w,
+                            hipStream_t st);
+// y = x * s (s read from device scalar: y = x / sqrt(*nrm2))
+hipError_t launch_normalize(int64_t n, const double *x, const double *nrm2, double *y,
+                            hipStream_t st);
+// sum over S blocks q of sum_rs K[kmap[q]][r][s] * S[q][s][r]  (Tr(K S)) partials
+hipError_t launch_trace_product(int b, int64_t nnzb_s, const int64_t *kmap_t, const double *K,
+                                const double *S, double *part, int nparts, hipStream_t st);
+hipError_t launch_convert(int dtype_out, int64_t n, const double *in, void *out, hipStream_t st);
+
+}  // namespace chess
