@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of the Chebyshev sparse matrix-function path on one MI355X.
+
+A step is one complete density-kernel evaluation (chess_fermi_operator) on
+the workload: spectral bounds, S^-1/2 chain, the orthogonal-frame transform,
+the Chebyshev chain(s) on H~', the mu search, and the post-transform with
+Tr(KS), inputs resident in HBM.
+
+Printed JSON line:
+  value        Chebyshev SpMM throughput in algorithmic GB/s: algorithmic
+               bytes of every chain-product launch in the timed steps divided
+               by their device time (HIP events on the library's stream);
+  ms_per_step  density-kernel time to solution of the fast form (float32
+               chain, Lanczos bounds checked by Eq. 6);
+  roofline     the chain product kernel against MI355X peaks;
+  cpu_baseline the oracle's chain (plain C, float64) on a bounded sample of
+               the same workload;
+  plain_f64    time to solution of the plain float64 form (Gershgorin bounds,
+               moments pass + bisection + accumulating pass) and the max-abs
+               difference of the two kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+METRIC = "Chebyshev SpMM GB/s + density-kernel time-to-solution vs plain FP64, at error ε"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def chain_step_cost(sysm, vbytes, n_acc, hist):
+    """Algorithmic bytes and flops of one chain-product launch.
+
+    Per value of the kernel pattern: read T_k and T_{k-1}, write T_{k+1}
+    (3 * vbytes), plus 16 bytes per float64 accumulator (read + write) and
+    vbytes per stored history copy.  Once per launch: the values of H~ and the
+    column indices of both patterns.  Flops: 2 b^3 per contributing block
+    triple (I, L, J)."""
+    b = sysm.b
+    nk = sysm.pat_k.nnzb * b * b
+    nh = sysm.pat_h.nnzb * b * b
+    per_val = 3 * vbytes + 16 * n_acc + (vbytes if hist else 0)
+    byts = nk * per_val + nh * vbytes + 4 * (sysm.pat_h.nnzb + sysm.pat_k.nnzb)
+    return byts
+
+
+def count_triples(sysm):
+    import numpy as np
+    import scipy.sparse as sp
+    nb = sysm.pat_h.nb
+    H = sp.csr_matrix((np.ones(sysm.pat_h.nnzb), sysm.pat_h.col_idx, sysm.pat_h.row_ptr), shape=(nb, nb))
+    K = sp.csr_matrix((np.ones(sysm.pat_k.nnzb), sysm.pat_k.col_idx, sysm.pat_k.row_ptr), shape=(nb, nb))
+    return float((K @ H).multiply(K).sum())
+
+
+def kernel_source_hash():
+    h = hashlib.sha1()
+    for f in ("kernels.hip", "kernels.h"):
+        h.update(open(os.path.join(ROOT, "paper_1704_00512_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(workload):
+    """HBM bytes per chain launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"chain_product_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha1:\s*(\w+)", text)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(sysm, budget_s=20.0):
+    """The oracle's float64 chain (one accumulator) on the host cores, timed on
+    a bounded number of Chebyshev steps of the same matrices."""
+    import numpy as np
+    from oracle import csr as ocsr
+    from oracle import pipeline as opl
+    ocsr.build_oracle()
+    H = opl.BlockMat(sysm.pat_h.nb, sysm.b, sysm.pat_h.row_ptr, sysm.pat_h.col_idx, sysm.H)
+    P = opl.BlockMat(sysm.pat_k.nb, sysm.b, sysm.pat_k.row_ptr, sysm.pat_k.col_idx)
+    Mt = opl.scaled(H.csr(), -3.0, 0.5)
+    Kc = P.pattern_csr()
+    coef = np.ones((1, 64)) * 1e-3
+    t0 = time.perf_counter()
+    ocsr.chebyshev(Mt, Kc, 64, coef, k_stop=3)  # one product
+    one = time.perf_counter() - t0
+    nprod = int(max(1, min(200, budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    ocsr.chebyshev(Mt, Kc, max(64, nprod + 2), np.ones((1, max(64, nprod + 2))) * 1e-3,
+                   k_stop=nprod + 2)
+    dt = time.perf_counter() - t0
+    byts = chain_step_cost(sysm, 8, 1, False)
+    return dict(value=round(byts * nprod / dt / 1e9, 3), unit="GB/s",
+                cores=ocsr.num_threads(), kind="oracle",
+                sample=f"{nprod} Chebyshev steps (masked product + axpby + 1 float64 accumulator) "
+                       f"of the oracle's scalar-CSR float64 chain on the same {sysm.n}-row H~ and "
+                       f"kernel pattern; {dt:.1f} s; bytes per step counted as for the GPU "
+                       f"kernel at float64 ({byts / 1e9:.3f} GB)",
+                ms_per_step=round(dt / nprod * 1e3, 2))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large80k")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the multi-GPU column-slab sharding is a design "
+              "(see DESIGN.md), not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1704_00512_amd import BlockPattern, Context, chess_fermi_operator
+    from workloads.generator import CONFIGS, make_config
+
+    log(f"generating workload {args.workload} {CONFIGS[args.workload]}")
+    t0 = time.time()
+    sysm = make_config(args.workload)
+    log(f"generated in {time.time() - t0:.1f} s: n={sysm.n} nnzb_H={sysm.pat_h.nnzb} "
+        f"nnzb_K={sysm.pat_k.nnzb}")
+    dev = torch.device("cuda:0")
+    H = torch.tensor(sysm.H, device=dev)
+    S = torch.tensor(sysm.S, device=dev)
+    ph = BlockPattern.from_host(sysm.b, sysm.pat_h.row_ptr, sysm.pat_h.col_idx, dev)
+    pk = BlockPattern.from_host(sysm.b, sysm.pat_k.row_ptr, sysm.pat_k.col_idx, dev)
+    K = pk.zeros()
+    ctx = Context(0)
+    fast = dict(precision="f32", bounds_mode="lanczos", store_history=1, tol_fit=1e-6,
+                tol_fit_s=1e-7)
+
+    def run(opts):
+        return chess_fermi_operator(ctx, H, ph, S, ph, pk, sysm.n_electrons, sysm.kT, out=K, **opts)
+
+    for i in range(args.warmup):
+        _, info = run(fast)
+        log(f"warmup {i}: {info['ms_total']:.1f} ms n_pl={info['n_pl']} passes={info['passes']} "
+            f"chain kernel {info['ms_chain_kernel']:.1f} ms")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, info = run(fast)
+        infos.append(info)
+        log(f"step {i}: {info['ms_total']:.1f} ms mu={info['mu']:.6f} n_pl={info['n_pl']} "
+            f"passes={info['passes']} bounds=[{info['lo']:.4f},{info['hi']:.4f}] "
+            f"trKS={info['tr_ks']:.6f} penalty={info['penalty']:.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    K_fast = K.cpu().numpy().copy()
+
+    # algorithmic accounting of the H~ chain launches (the dominant kernel)
+    info = infos[-1]
+    n_pl, passes = info["n_pl"], info["passes"]
+    hist = passes == 1
+    steps_per_pass = max(n_pl - 2, 0)
+    b1 = chain_step_cost(sysm, 4, 0, hist)
+    b2 = chain_step_cost(sysm, 4, 1, False)
+    bytes_call = steps_per_pass * b1 + (0 if hist else steps_per_pass * b2)
+    launches_call = steps_per_pass * passes
+    log("counting block triples for the flop count")
+    triples = count_triples(sysm)
+    flops_launch = 2.0 * sysm.b ** 3 * triples
+    kern_ms = sum(i["ms_chain_kernel"] for i in infos) / len(infos)
+    gbs = bytes_call / (kern_ms * 1e-3) / 1e9
+    tflops = flops_launch * launches_call / (kern_ms * 1e-3) / 1e12
+    t_hbm = bytes_call / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops_launch * launches_call / (FP32_PEAK_TFLOPS * 1e12)
+    bound = "hbm" if t_hbm >= t_alu else "alu"
+    avg_launch_ms = kern_ms / max(launches_call, 1)
+    traffic = measured_traffic(args.workload)
+    if bound == "hbm":
+        roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(gbs / HBM_PEAK_GBS, 4))
+    else:
+        roof = dict(bound="alu", achieved=round(tflops, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(tflops / FP32_PEAK_TFLOPS, 4))
+    roof.update(traffic=traffic, kernel="k_masked_product<float,4,4>",
+                avg_launch_ms=round(avg_launch_ms, 4),
+                algorithmic_bytes_per_call=int(bytes_call), launches_per_call=launches_call,
+                flops_per_launch=flops_launch, achieved_gbs=round(gbs, 1),
+                achieved_tflops=round(tflops, 2), t_hbm_ideal_ms=round(t_hbm * 1e3, 2),
+                t_alu_ideal_ms=round(t_alu * 1e3, 2), kernel_source_sha1=kernel_source_hash())
+
+    out = dict(metric=METRIC, value=round(gbs, 1), unit="GB/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms_per_step, 2), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=f"{args.workload}: {sysm.meta['n_atoms']} atoms x {sysm.b} = "
+                                    f"{sysm.n} rows, P_H {sysm.pat_h.nnzb} blocks, P_K "
+                                    f"{sysm.pat_k.nnzb} blocks, kT {sysm.kT} Ha, erfc, "
+                                    f"N_e {sysm.n_electrons:g}",
+                           form="float32 chain, Lanczos bounds + Eq. 6 check, tol_fit 1e-6",
+                           n_pl=n_pl, n_pl_s=info["n_pl_s"], passes=passes,
+                           time_to_solution_ms=round(ms_per_step, 2)),
+               roofline=roof)
+
+    if not args.no_plain:
+        log("plain float64 form (Gershgorin bounds, two passes)")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, pinfo = run(dict(precision="f64", bounds_mode="gershgorin", store_history=0))
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) * 1e3
+        K_plain = K.cpu().numpy()
+        diff = float(np.max(np.abs(K_plain - K_fast)))
+        out["plain_f64"] = dict(ms=round(tp, 1), n_pl=pinfo["n_pl"], passes=pinfo["passes"],
+                                bounds=[pinfo["lo"], pinfo["hi"]], mu=pinfo["mu"],
+                                max_abs_diff_fast_vs_plain=diff,
+                                speedup_fast_vs_plain=round(tp / ms_per_step, 2))
+        log(f"plain f64: {tp:.0f} ms n_pl={pinfo['n_pl']} max|K_fast-K_plain|={diff:.2e}")
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(sysm)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,7 +20,7 @@ Readings (all choices the paper leaves open):
   * S_AA = I_b, S_AB = exp(-r^2/8) (I_b + 0.05 G) with G iid N(0,1) per
     unordered pair, S_BA = S_AB^T; then S <- a S + c I maps its extreme
     eigenvalues onto [0.3, 2.0] exactly (dense eigvalsh up to 9000 rows,
-    otherwise Lanczos to 1e-12);
+    otherwise implicitly restarted Lanczos to a relative 1e-8);
   * H_AA = diag(U[-0.7, -0.3]) per basis function, H_AB = -0.3 exp(-r/2)
     (I_b + 0.05 G'), mirrored;
   * S and H both live on the pattern with cutoff r_H; the kernel pattern uses
@@ -259,8 +259,8 @@ def extreme_eigenvalues(pat: BlockPattern, val: np.ndarray) -> tuple[float, floa
         w = scipy.linalg.eigvalsh(to_dense(pat, val))
         return float(w[0]), float(w[-1])
     A = to_scipy(pat, val)
-    lo = scipy.sparse.linalg.eigsh(A, k=1, which="SA", tol=1e-12, return_eigenvectors=False)[0]
-    hi = scipy.sparse.linalg.eigsh(A, k=1, which="LA", tol=1e-12, return_eigenvectors=False)[0]
+    lo = scipy.sparse.linalg.eigsh(A, k=1, which="SA", tol=1e-8, ncv=64, return_eigenvectors=False)[0]
+    hi = scipy.sparse.linalg.eigsh(A, k=1, which="LA", tol=1e-8, ncv=64, return_eigenvectors=False)[0]
     return float(lo), float(hi)
 
 
