@@ -27,6 +27,7 @@
 #include <limits>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/chess.h"
@@ -130,7 +131,16 @@ struct ProductPlan {
     const Pattern *a = nullptr, *bt = nullptr, *c = nullptr;
     int dtype = 0;
     ProductPlanDev dev;
-    DevBuf d_tile_row0, d_u_off, d_u_cols, d_u_pos, d_j_off, d_j_cols, d_j_pos;
+    DevBuf d_tile_row0, d_u_off, d_u_cols, d_u_pos, d_j_off, d_j_cols, d_j_pos, d_j_rec;
+};
+
+// Product with precomputed hit lists (kernels_listed.hip), for chains.
+struct ListedPlan {
+    const Pattern *a = nullptr, *bt = nullptr, *c = nullptr;
+    int dtype = 0;
+    bool usable = false;  // false: rows too long for the list format
+    ListedPlanDev dev;
+    DevBuf d_tile_row0, d_j_off, d_j_rec, d_entries;
 };
 
 }  // namespace chess
@@ -142,6 +152,7 @@ struct chess_ctx {
     std::vector<std::unique_ptr<chess::Pattern>> patterns;
     std::vector<std::unique_ptr<chess::EmbedMap>> embeds;
     std::vector<std::unique_ptr<chess::ProductPlan>> plans;
+    std::vector<std::unique_ptr<chess::ListedPlan>> lplans;
 };
 
 namespace chess {
@@ -249,7 +260,9 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
     const int b = A->b;
     const int cmax = pick_cmax(dtype, b);
     const size_t block_bytes = (size_t)b * b * (dtype == 1 ? 4 : 8);
-    const int budget_blocks = std::max<int>((int)(49152 / block_bytes), A->max_row);
+    // LDS budget for the staged A tile: 48 KB (float32) or 80 KB (float64)
+    const size_t a_budget = dtype == 1 ? 49152 : 81920;
+    const int budget_blocks = std::max<int>((int)(a_budget / block_bytes), A->max_row);
     std::vector<int32_t> tile_row0;
     std::vector<int64_t> u_off{0}, j_off{0};
     std::vector<int32_t> u_cols, j_cols;
@@ -306,6 +319,15 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
         j_off.push_back((int64_t)j_cols.size());
     }
     tile_row0.push_back(A->nb);
+    if (Bt->nnzb >= ((int64_t)1 << 31)) CHESS_THROW(CHESS_E_UNSUPPORTED, "Bt pattern has 2^31 or more blocks");
+    std::vector<int32_t> j_rec(j_cols.size() * 4);
+    for (size_t x = 0; x < j_cols.size(); ++x) {
+        const int j = j_cols[x];
+        j_rec[4 * x] = j;
+        j_rec[4 * x + 1] = (int32_t)Bt->rp[j];
+        j_rec[4 * x + 2] = (int32_t)(Bt->rp[j + 1] - Bt->rp[j]);
+        j_rec[4 * x + 3] = 0;
+    }
     if (max_u >= 32767) CHESS_THROW(CHESS_E_UNSUPPORTED, "row tile with %d distinct columns", max_u);
     int hl = 1;
     while ((1 << hl) < 2 * max_u) ++hl;
@@ -317,6 +339,7 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
     upload(P->d_j_off, j_off, st);
     upload(P->d_j_cols, j_cols, st);
     upload(P->d_j_pos, j_pos, st);
+    upload(P->d_j_rec, j_rec, st);
     HIPCHECK(hipStreamSynchronize(st));
     ProductPlanDev &d = P->dev;
     d.ntiles = (int)tile_row0.size() - 1;
@@ -324,6 +347,7 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
     d.hcap_log2 = hl;
     d.lds_ablocks = lds_ablocks;
     d.max_u = max_u;
+    d.max_bt_row = Bt->max_row;
     d.tile_row0 = P->d_tile_row0.as<int32_t>();
     d.u_off = P->d_u_off.as<int64_t>();
     d.u_cols = P->d_u_cols.as<int32_t>();
@@ -331,10 +355,193 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
     d.j_off = P->d_j_off.as<int64_t>();
     d.j_cols = P->d_j_cols.as<int32_t>();
     d.j_pos = P->d_j_pos.as<uint16_t>();
+    d.j_rec = P->d_j_rec.as<int32_t>();
+    // stage Bt rows in LDS when it fits next to the A tile
+    d.stage_bt = (b == 4 && Bt->max_row <= 128) ? 1 : 0;
+    if (masked_product_lds_bytes(dtype, b, d) > 160 * 1024) d.stage_bt = 0;
     const size_t lds = masked_product_lds_bytes(dtype, b, d);
     if (lds > 160 * 1024) CHESS_THROW(CHESS_E_UNSUPPORTED, "product tile needs %zu bytes of LDS", lds);
     ctx->plans.push_back(std::move(P));
     return ctx->plans.back().get();
+}
+
+// Symbolic plan with hit lists for C = P_C o (A Bt^T) (see kernels.h,
+// ListedPlanDev).  The intersections of sorted rows are computed once here, in
+// parallel over tiles.  Returns a plan with usable = false when a row is too
+// long for the list format; callers then use the searching kernel.
+static const ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Pattern *Bt,
+                                         const Pattern *C, int dtype) {
+    for (auto &e : ctx->lplans)
+        if (e->a == A && e->bt == Bt && e->c == C && e->dtype == dtype) return e.get();
+    auto P = std::make_unique<ListedPlan>();
+    P->a = A;
+    P->bt = Bt;
+    P->c = C;
+    P->dtype = dtype;
+    const int b = A->b;
+    const int cmax = pick_cmax(dtype, b);
+    const int ew = (A->max_row <= 255 && Bt->max_row <= 255) ? 1 : 2;
+    const int max_col_entries = ew == 1 ? 512 : 256;  // LDS list area of a wave: 1 KB
+    if (A->max_row > 65535 || Bt->max_row > 65535 || (b == 4 && Bt->max_row > 128) ||
+        Bt->nnzb >= ((int64_t)1 << 31)) {
+        ctx->lplans.push_back(std::move(P));
+        return ctx->lplans.back().get();
+    }
+    const size_t block_bytes = (size_t)b * b * (dtype == 1 ? 4 : 8);
+    // A tile budget: room for CMAX rows of the longest row when that fits
+    // (float32 up to 96 KB, float64 up to 80 KB), so tiles are rarely short
+    const size_t a_cap = dtype == 1 ? 98304 : 81920;
+    const size_t a_budget = std::max<size_t>(dtype == 1 ? 49152 : 40960,
+                                             std::min<size_t>(a_cap, (size_t)cmax * A->max_row * block_bytes));
+    const int budget_blocks = std::max<int>((int)(a_budget / block_bytes), A->max_row);
+    std::vector<int32_t> tile_row0;
+    int lds_ablocks = 0;
+    for (int r = 0; r < A->nb;) {
+        const int row0 = r;
+        int64_t blocks = 0;
+        while (r < A->nb && r - row0 < cmax) {
+            const int64_t len = A->rp[r + 1] - A->rp[r];
+            if (r > row0 && blocks + len > budget_blocks) break;
+            blocks += len;
+            ++r;
+        }
+        tile_row0.push_back(row0);
+        lds_ablocks = std::max<int>(lds_ablocks, (int)blocks);
+    }
+    const int ntiles = (int)tile_row0.size();
+    tile_row0.push_back(A->nb);
+    struct TileOut {
+        std::vector<int32_t> rec;      // 8 per column; entry offsets relative to the tile
+        std::vector<uint16_t> ent;     // entry_width 1
+        std::vector<uint32_t> ent32;   // entry_width 2
+        bool overflow = false;
+    };
+    std::vector<TileOut> outs(ntiles);
+    auto work = [&](int t0, int t1) {
+        std::vector<int32_t> cols;
+        for (int t = t0; t < t1; ++t) {
+            TileOut &o = outs[t];
+            const int row0 = tile_row0[t], c = tile_row0[t + 1] - row0;
+            cols.assign(C->ci.begin() + C->rp[row0], C->ci.begin() + C->rp[row0 + c]);
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            for (int j : cols) {
+                const int64_t first = ew == 1 ? (int64_t)o.ent.size() : (int64_t)o.ent32.size();
+                int32_t counts = 0;
+                uint32_t pos01 = 0xFFFFFFFFu, pos23 = 0xFFFFFFFFu;
+                int total = 0;
+                for (int i = 0; i < c; ++i) {
+                    const int row = row0 + i;
+                    const int64_t q = C->find(row, j);
+                    if (q < 0) continue;
+                    const uint32_t op = (uint32_t)(q - C->rp[row]);
+                    if (i < 2)
+                        pos01 = (pos01 & ~(0xFFFFu << (16 * i))) | (op << (16 * i));
+                    else
+                        pos23 = (pos23 & ~(0xFFFFu << (16 * (i - 2)))) | (op << (16 * (i - 2)));
+                    // sorted intersection of A row `row` with Bt row j
+                    int64_t pa = A->rp[row], pe = A->rp[row + 1];
+                    int64_t pb = Bt->rp[j], be = Bt->rp[j + 1];
+                    int n = 0;
+                    while (pa < pe && pb < be) {
+                        const int ca = A->ci[pa], cb = Bt->ci[pb];
+                        if (ca < cb) {
+                            ++pa;
+                        } else if (cb < ca) {
+                            ++pb;
+                        } else {
+                            const uint32_t ra = (uint32_t)(pa - A->rp[row]);
+                            const uint32_t rbt = (uint32_t)(pb - Bt->rp[j]);
+                            if (ew == 1)
+                                o.ent.push_back((uint16_t)(ra | (rbt << 8)));
+                            else
+                                o.ent32.push_back(ra | (rbt << 16));
+                            ++n;
+                            ++pa;
+                            ++pb;
+                        }
+                    }
+                    if (n > 255) o.overflow = true;
+                    counts |= (n & 0xFF) << (8 * i);
+                    total += n;
+                }
+                if (total > max_col_entries) o.overflow = true;
+                // keep every column's entries 4-byte aligned
+                if (ew == 1 && (o.ent.size() & 1)) o.ent.push_back(0);
+                o.rec.insert(o.rec.end(), {j, (int32_t)Bt->rp[j], (int32_t)(Bt->rp[j + 1] - Bt->rp[j]),
+                                           (int32_t)first, counts, (int32_t)pos01, (int32_t)pos23, 0});
+            }
+        }
+    };
+    const int nthr = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    const int chunk = (ntiles + nthr - 1) / nthr;
+    for (int k = 0; k < nthr; ++k) {
+        const int t0 = k * chunk, t1 = std::min(ntiles, t0 + chunk);
+        if (t0 < t1) pool.emplace_back(work, t0, t1);
+    }
+    for (auto &th : pool) th.join();
+    std::vector<int64_t> j_off(ntiles + 1, 0);
+    int64_t tot_ent = 0, tot_col = 0;
+    for (int t = 0; t < ntiles; ++t) {
+        if (outs[t].overflow) {
+            ctx->lplans.push_back(std::move(P));
+            return ctx->lplans.back().get();
+        }
+        j_off[t + 1] = j_off[t] + (int64_t)outs[t].rec.size() / 8;
+        tot_col += (int64_t)outs[t].rec.size() / 8;
+        tot_ent += ew == 1 ? (int64_t)outs[t].ent.size() : (int64_t)outs[t].ent32.size();
+    }
+    if (tot_ent >= ((int64_t)1 << 31)) {
+        ctx->lplans.push_back(std::move(P));
+        return ctx->lplans.back().get();
+    }
+    std::vector<int32_t> rec((size_t)tot_col * 8);
+    std::vector<uint16_t> ent;
+    std::vector<uint32_t> ent32;
+    if (ew == 1) ent.resize((size_t)tot_ent); else ent32.resize((size_t)tot_ent);
+    int64_t ebase = 0;
+    for (int t = 0; t < ntiles; ++t) {
+        TileOut &o = outs[t];
+        const size_t nrec = o.rec.size() / 8;
+        for (size_t x = 0; x < nrec; ++x) {
+            int32_t *r = &rec[(size_t)(j_off[t] + x) * 8];
+            std::copy(o.rec.begin() + 8 * x, o.rec.begin() + 8 * x + 8, r);
+            r[3] = (int32_t)(r[3] + ebase);
+        }
+        if (ew == 1) {
+            std::copy(o.ent.begin(), o.ent.end(), ent.begin() + ebase);
+            ebase += (int64_t)o.ent.size();
+        } else {
+            std::copy(o.ent32.begin(), o.ent32.end(), ent32.begin() + ebase);
+            ebase += (int64_t)o.ent32.size();
+        }
+        std::vector<int32_t>().swap(o.rec);
+        std::vector<uint16_t>().swap(o.ent);
+        std::vector<uint32_t>().swap(o.ent32);
+    }
+    // pad so that the last column's 4-word prefetch stays inside the buffer
+    if (ew == 1) ent.resize(ent.size() + 1024, 0); else ent32.resize(ent32.size() + 512, 0);
+    hipStream_t st = ctx->stream;
+    upload(P->d_tile_row0, tile_row0, st);
+    upload(P->d_j_off, j_off, st);
+    upload(P->d_j_rec, rec, st);
+    if (ew == 1) upload(P->d_entries, ent, st); else upload(P->d_entries, ent32, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    ListedPlanDev &d = P->dev;
+    d.ntiles = ntiles;
+    d.cmax = cmax;
+    d.lds_ablocks = lds_ablocks;
+    d.max_bt_row = Bt->max_row;
+    d.max_entries = max_col_entries;
+    d.entry_width = ew;
+    d.tile_row0 = P->d_tile_row0.as<int32_t>();
+    d.j_off = P->d_j_off.as<int64_t>();
+    d.j_rec = P->d_j_rec.as<int32_t>();
+    d.entries = P->d_entries.p;
+    P->usable = listed_product_lds_bytes(dtype, b, d) <= 160 * 1024;
+    ctx->lplans.push_back(std::move(P));
+    return ctx->lplans.back().get();
 }
 
 // C = P_C o (A Bt^T) with an epilogue.  A, Bt, C value arrays in dtype.
@@ -349,6 +556,19 @@ static void product(chess_ctx *ctx, int dtype, const ProductPlan *plan, const vo
     ops.c_rp = plan->c->d_rp.as<int64_t>();
     ops.c_out = c;
     HIPCHECK(launch_masked_product(dtype, plan->a->b, plan->dev, ops, ep, ctx->stream));
+}
+
+static void product_listed(chess_ctx *ctx, int dtype, const ListedPlan *plan, const void *a,
+                           const void *bt, void *c, const Epilogue &ep) {
+    ProductOperands ops;
+    ops.a_rp = plan->a->d_rp.as<int64_t>();
+    ops.a_val = a;
+    ops.bt_rp = plan->bt->d_rp.as<int64_t>();
+    ops.bt_ci = plan->bt->d_ci.as<int32_t>();
+    ops.bt_val = bt;
+    ops.c_rp = plan->c->d_rp.as<int64_t>();
+    ops.c_out = c;
+    HIPCHECK(launch_listed_product(dtype, plan->a->b, plan->dev, ops, ep, ctx->stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -479,9 +699,11 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     const int dtype = rq.dtype;
     const int64_t nK = PK->nnzb * b * b;
     const EmbedMap *emb = get_embed(ctx, PM, PK, "M~ in the chain pattern");
-    const ProductPlan *plan = get_plan(ctx, PK, PM, PK, dtype);
+    const ListedPlan *lplan = get_listed_plan(ctx, PK, PM, PK, dtype);
+    const ProductPlan *plan = lplan->usable ? nullptr : get_plan(ctx, PK, PM, PK, dtype);
     const size_t tb = vbytes(PK, dtype);
-    DevBuf U0(tb), U1(tb), Bt(vbytes(PM, dtype));
+    // Bt gets 16 KB of slack: the listed kernel reads whole 64-lane rounds of a row
+    DevBuf U0(tb), U1(tb), Bt(vbytes(PM, dtype) + 16384);
     // Bt = M~^T on PM (row j of Bt = column j of M~)
     HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, PM->d_tmap.as<int64_t>(), rq.Mt, Bt.p, 1, st));
     // U_0 = I, U_1 = M~^T placed in PK
@@ -498,7 +720,7 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
         if (rq.n_pl > 1)
             HIPCHECK(hipMemcpyAsync((char *)rq.hist + tb, U1.p, tb, hipMemcpyDeviceToDevice, st));
     }
-    const int ntiles = plan->dev.ntiles;
+    const int ntiles = lplan->usable ? lplan->dev.ntiles : plan->dev.ntiles;
     const int nsteps = std::max(rq.n_pl, 2);
     DevBuf part(sizeof(double) * (size_t)nsteps * std::max(ntiles, 256));
     DevBuf mom(sizeof(double) * nsteps);
@@ -526,7 +748,10 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
         }
         ep.hist = rq.hist ? (char *)rq.hist + (size_t)(k + 1) * tb : nullptr;
         ep.trace_partial = pd + (size_t)(k + 1) * ntiles;
-        product(ctx, dtype, plan, ucur, Bt.p, uprev, ep);
+        if (lplan->usable)
+            product_listed(ctx, dtype, lplan, ucur, Bt.p, uprev, ep);
+        else
+            product(ctx, dtype, plan, ucur, Bt.p, uprev, ep);
         std::swap(ucur, uprev);
     }
     rq.kernel_ms = tm.stop();

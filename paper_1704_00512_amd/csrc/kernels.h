@@ -21,6 +21,8 @@ struct ProductPlanDev {
     int hcap_log2 = 0;     // LDS hash table size = 1 << hcap_log2
     int lds_ablocks = 0;   // largest A tile in blocks
     int max_u = 0;         // largest u list
+    int max_bt_row = 0;    // longest row of Bt (per-wave LDS staging)
+    int stage_bt = 0;      // 1: each wave copies its Bt row to LDS first
     const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
     const int64_t *u_off = nullptr;      // [ntiles + 1]
     const int32_t *u_cols = nullptr;
@@ -28,6 +30,7 @@ struct ProductPlanDev {
     const int64_t *j_off = nullptr;      // [ntiles + 1]
     const int32_t *j_cols = nullptr;
     const uint16_t *j_pos = nullptr;     // [total_j * cmax]
+    const int32_t *j_rec = nullptr;      // [total_j * 4]: j, Bt row start, Bt row length, 0
 };
 
 // Epilogue applied to Y = P_C o (A Bt^T) at every output element:
@@ -57,6 +60,31 @@ struct ProductOperands {
     const int64_t *c_rp;
     void *c_out;
 };
+
+// Plan of a product with precomputed hit lists (kernels_listed.hip).  Per
+// tile the output columns j; per column a record of 8 int32:
+//   {j, Bt row start, Bt row length, first entry,
+//    hit counts of tile rows 0..3 (8 bits each), out pos rows 0|1, 2|3, 0}
+// where "out pos" is the block's offset in the output row (0xFFFF: absent).
+// Entries (entry_width 1: 8-bit position in A row i | 8-bit position in Bt
+// row j << 8; entry_width 2: 16 + 16 bits) are grouped per column, row 0's
+// hits first; every column's group starts on a 4-byte boundary.
+struct ListedPlanDev {
+    int ntiles = 0;
+    int cmax = 0;
+    int lds_ablocks = 0;
+    int max_bt_row = 0;
+    int max_entries = 0;
+    int entry_width = 1;
+    const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
+    const int64_t *j_off = nullptr;      // [ntiles + 1]
+    const int32_t *j_rec = nullptr;      // [total_j * 8]
+    const void *entries = nullptr;
+};
+
+hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
+                                 const ProductOperands &ops, const Epilogue &ep, hipStream_t st);
+size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan);
 
 // dtype: 0 = double, 1 = float.  Returns a hipError_t.
 hipError_t launch_masked_product(int dtype, int b, const ProductPlanDev &plan,

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace chess {
@@ -71,45 +73,85 @@ __device__ inline double wave_max(double v) {
 // masked block product
 // ---------------------------------------------------------------------------
 
-template <typename T, int B, int CMAX>
-__global__ __launch_bounds__(kWG) void k_masked_product(ProductPlanDev plan, ProductOperands ops,
-                                                        Epilogue ep) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+// LDS layout of one workgroup (all regions 16-byte aligned):
+//   A tile      lds_ablocks * B*B * T   this tile's rows of A
+//   hash keys   hcap * int              column l -> index k into the u list
+//   hash vals   hcap * short
+//   upos        max_u * CMAX * ushort   k -> position of A[i, l] in the tile
+//   per wave:   Bt row staging (max_bt_row * B*B * T, only when the row is
+//               prefetched through registers) and CMAX hit lists of
+//               max_bt_row packed (Bt slot << 16 | A tile position) entries
+struct LdsLayout {
+    size_t a, hkey, hval, upos, wave, wave_bt, wave_list, total;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+template <typename T, int B, int CMAX, int NW, bool PREF>
+__host__ __device__ inline LdsLayout lds_layout(const ProductPlanDev &plan) {
+    LdsLayout L;
+    const size_t hcap = (size_t)1 << plan.hcap_log2;
+    L.a = 0;
+    L.hkey = align16((size_t)plan.lds_ablocks * B * B * sizeof(T));
+    L.hval = L.hkey + align16(hcap * 4);
+    L.upos = L.hval + align16(hcap * 2);
+    L.wave = L.upos + align16((size_t)plan.max_u * CMAX * 2);
+    L.wave_bt = PREF ? align16((size_t)plan.max_bt_row * B * B * sizeof(T)) : 0;
+    L.wave_list = align16((size_t)plan.max_bt_row * CMAX * 4);
+    L.total = L.wave + (size_t)NW * (L.wave_bt + L.wave_list);
+    return L;
+}
+
+__device__ inline void wave_lds_sync() {
+    // orders this wave's LDS writes before its later LDS reads (and the reverse)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NT>
+__device__ inline double block_sum_n(double v) {
+    __shared__ double red[NT / 64];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// Copies this tile's rows of A to LDS and builds the LDS hash of its columns.
+template <typename T, int B, int CMAX, int NT>
+__device__ inline void stage_tile(const ProductPlanDev &plan, const ProductOperands &ops,
+                                  unsigned char *smem, const LdsLayout &L, int tile, int row0,
+                                  int c) {
     constexpr int BB = B * B;
-    constexpr int NEL = CMAX * BB;
-    constexpr int NE = (NEL + 63) / 64;
-
-    const int ntiles = plan.ntiles;
-    const int nt8 = (ntiles + 7) & ~7;
-    const int w = blockIdx.x;
-    // XCD-aware mapping: workgroup w runs on XCD w % 8; give each XCD a
-    // contiguous range of tiles.
-    const int tile = (w & 7) * (nt8 >> 3) + (w >> 3);
-    if (tile >= ntiles) return;
-
-    const int row0 = plan.tile_row0[tile];
-    const int c = plan.tile_row0[tile + 1] - row0;
     const int64_t ab0 = ops.a_rp[row0];
     const int nab = (int)(ops.a_rp[row0 + c] - ab0);
     const int hcap = 1 << plan.hcap_log2;
-    const unsigned hmask = (unsigned)hcap - 1u;
-
-    T *As = reinterpret_cast<T *>(smem);
-    int *hkey = reinterpret_cast<int *>(smem + (size_t)plan.lds_ablocks * BB * sizeof(T));
-    short *hval = reinterpret_cast<short *>(hkey + hcap);
-    unsigned short *upos = reinterpret_cast<unsigned short *>(hval + hcap);
-
-    // stage this tile's rows of A (contiguous in block CSR)
-    {
-        const T *Ag = reinterpret_cast<const T *>(ops.a_val) + ab0 * BB;
+    T *As = reinterpret_cast<T *>(smem + L.a);
+    int *hkey = reinterpret_cast<int *>(smem + L.hkey);
+    short *hval = reinterpret_cast<short *>(smem + L.hval);
+    unsigned short *upos = reinterpret_cast<unsigned short *>(smem + L.upos);
+    const T *Ag = reinterpret_cast<const T *>(ops.a_val) + ab0 * BB;
+    if ((BB * sizeof(T)) % 16 == 0) {
+        // b = 4: blocks are whole 16-byte chunks and start 16-byte aligned
+        const uint4 *src = reinterpret_cast<const uint4 *>(Ag);
+        uint4 *dst = reinterpret_cast<uint4 *>(As);
+        const int n16 = (int)((size_t)nab * BB * sizeof(T) / 16);
+        for (int x = threadIdx.x; x < n16; x += NT) dst[x] = src[x];
+    } else {
         const int n = nab * BB;
-        for (int x = threadIdx.x; x < n; x += kWG) As[x] = Ag[x];
-        for (int x = threadIdx.x; x < hcap; x += kWG) hkey[x] = -1;
+        for (int x = threadIdx.x; x < n; x += NT) As[x] = Ag[x];
     }
+    for (int x = threadIdx.x; x < hcap; x += NT) hkey[x] = -1;
     __syncthreads();
     const int64_t u0 = plan.u_off[tile];
     const int nu = (int)(plan.u_off[tile + 1] - u0);
-    for (int k = threadIdx.x; k < nu; k += kWG) {
+    const unsigned hmask = (unsigned)hcap - 1u;
+    for (int k = threadIdx.x; k < nu; k += NT) {
         const int col = plan.u_cols[u0 + k];
         unsigned h = hash_slot(col, plan.hcap_log2);
         while (true) {
@@ -124,118 +166,389 @@ __global__ __launch_bounds__(kWG) void k_masked_product(ProductPlanDev plan, Pro
         for (int i = 0; i < CMAX; ++i) upos[k * CMAX + i] = plan.u_pos[(u0 + k) * CMAX + i];
     }
     __syncthreads();
+}
+
+// Epilogue for one output element (see Epilogue in kernels.h); the operands
+// read from memory were loaded ahead (prevv, accv).
+template <typename T>
+__device__ inline void store_output(const ProductOperands &ops, const Epilogue &ep, int64_t off,
+                                    T y, T prevv, const double (&accv)[4], bool diag,
+                                    double &tr) {
+    T o = (T)ep.alpha * y;
+    if (ep.prev) o = fma((T)ep.beta, prevv, o);
+    reinterpret_cast<T *>(ops.c_out)[off] = o;
+    const double od = (double)o;
+#pragma unroll
+    for (int qa = 0; qa < 4; ++qa)
+        if (qa < ep.nacc) ep.acc[qa][off] = accv[qa] + ep.coef[qa] * od;
+    if (ep.hist) reinterpret_cast<T *>(ep.hist)[off] = o;
+    if (diag) tr += od;
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// The product kernel.  One workgroup per tile of <= CMAX consecutive output
+// rows, NW waves; each wave takes output columns j of the tile in turn.  Per
+// column: look up every l of row j of Bt in the tile's hash (one lane per l),
+// compact the hits of each tile row into an LDS list (ballot + popcount),
+// then accumulate Y[i, j] = sum over hits A[i, l] Bt[j, l]^T:
+//   MFMA (float, b = 4, CMAX = 4): v_mfma_f32_4x4x1f32 runs 16 independent
+//     4x4 outer products; slot g16 = lane / 4 = 4 i + grp takes tile row i and
+//     every 4th hit (offset grp) of its list; lane (g16, q) feeds row q of
+//     A[i, l] (A operand) and row q of Bt[j, l] (B operand); four MFMAs
+//     (k = t = 0..3) form the block product; the four groups of a row are
+//     summed across lanes at the end.  Output register v is row v, lane q is
+//     column q of the slot's block.
+//   VALU (all other types and b): one output element (i, r, s) per lane
+//     (several for b = 9), dot products of row r of A[i, l] and row s of Bt[j, l].
+// Latency hiding: the (j, Bt row start, length) record of column jj + 2 NW and
+// the column indices (and, with PREF, the values) of row j of column jj + NW
+// are in flight while column jj is computed; the epilogue operands of column
+// jj are loaded before its hits are built.
+template <typename T, int B, int CMAX, int NW, bool MFMA, bool PREF>
+__global__ __launch_bounds__(64 * NW) void k_product(ProductPlanDev plan, ProductOperands ops,
+                                                     Epilogue ep) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int BB = B * B;
+    constexpr int NT = 64 * NW;
+    constexpr int NE = MFMA ? 1 : (CMAX * BB + 63) / 64;
+    constexpr int V16 = (BB * (int)sizeof(T)) / 16;          // 16-byte chunks per block (b = 4)
+    constexpr int RBV = PREF ? (128 * V16 + 63) / 64 : 1;    // chunks per lane, rows <= 128 blocks
+    static_assert(!MFMA || (B == 4 && CMAX == 4 && sizeof(T) == 4), "MFMA path: float, b = 4");
+    static_assert(!PREF || B == 4, "register prefetch of Bt rows: b = 4");
+
+    const int ntiles = plan.ntiles;
+    const int nt8 = (ntiles + 7) & ~7;
+    const int w = blockIdx.x;
+    // XCD-aware mapping: workgroup w runs on XCD w % 8; give each XCD a
+    // contiguous range of tiles so neighbouring tiles share that XCD's L2.
+    const int tile = (w & 7) * (nt8 >> 3) + (w >> 3);
+    if (tile >= ntiles) return;
+    const LdsLayout L = lds_layout<T, B, CMAX, NW, PREF>(plan);
+    const int row0 = plan.tile_row0[tile];
+    const int c = plan.tile_row0[tile + 1] - row0;
+    stage_tile<T, B, CMAX, NT>(plan, ops, smem, L, tile, row0, c);
 
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    const T *As = reinterpret_cast<const T *>(smem + L.a);
+    unsigned char *wbase = smem + L.wave + (size_t)wave * (L.wave_bt + L.wave_list);
+    T *btw = reinterpret_cast<T *>(wbase);
+    uint32_t *lists = reinterpret_cast<uint32_t *>(wbase + L.wave_bt);
+    const int *hkey = reinterpret_cast<const int *>(smem + L.hkey);
+    const short *hval = reinterpret_cast<const short *>(smem + L.hval);
+    const unsigned short *upos = reinterpret_cast<const unsigned short *>(smem + L.upos);
+    const unsigned hmask = (1u << plan.hcap_log2) - 1u;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int LS = plan.max_bt_row;
 
+    // output elements of this lane: (tile row, row in block, column in block)
     int ei[NE], er[NE], es[NE];
     int64_t cbase[NE];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
-        const int e = lane + 64 * q;
-        ei[q] = e / BB;
-        er[q] = (e % BB) / B;
-        es[q] = e % B;
-        cbase[q] = (ei[q] < c) ? ops.c_rp[row0 + ei[q]] : -1;
+        if (MFMA) {
+            ei[q] = lane >> 4;        // slot / 4
+            er[q] = (lane >> 2) & 3;  // hit group = output row written
+            es[q] = lane & 3;
+        } else {
+            const int e = lane + 64 * q;
+            ei[q] = e / BB;
+            er[q] = (e % BB) / B;
+            es[q] = e % B;
+        }
+        cbase[q] = (ei[q] < c) ? ops.c_rp[row0 + ei[q]] : 0;
     }
 
     const int64_t j0 = plan.j_off[tile];
     const int nj = (int)(plan.j_off[tile + 1] - j0);
-    const T *Bt = reinterpret_cast<const T *>(ops.bt_val);
-    T *Cout = reinterpret_cast<T *>(ops.c_out);
+    const int4 *recs = reinterpret_cast<const int4 *>(plan.j_rec);
+    const T *BtV = reinterpret_cast<const T *>(ops.bt_val);
     const T *Prev = reinterpret_cast<const T *>(ep.prev);
-    T *Hist = reinterpret_cast<T *>(ep.hist);
-    const T alpha = (T)ep.alpha;
-    const T beta = (T)ep.beta;
     double tr = 0.0;
 
-    for (int jj = wave; jj < nj; jj += kWG / 64) {
-        const int j = plan.j_cols[j0 + jj];
-        int64_t outp[NE];
-        T acc[NE];
+    // pipeline registers: record of the current and next column, column
+    // indices and (PREF) values of the current column's Bt row
+    int4 rec = make_int4(-1, 0, 0, 0), recN = make_int4(-1, 0, 0, 0);
+    uint2 pos = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu), posN = pos;
+    int ci0 = -1, ci1 = -1;
+    uint4 bt[RBV];
+#define CHESS_LOAD_REC(JJ, R, P)                                                              \
+    do {                                                                                       \
+        if ((JJ) < nj) {                                                                       \
+            R = recs[j0 + (JJ)];                                                               \
+            const unsigned short *jp_ = plan.j_pos + (j0 + (JJ)) * CMAX;                       \
+            uint32_t v0_ = jp_[0], v1_ = CMAX > 1 ? jp_[1 % CMAX] : 0xFFFFu;                   \
+            uint32_t v2_ = CMAX > 2 ? jp_[2 % CMAX] : 0xFFFFu, v3_ = CMAX > 3 ? jp_[3 % CMAX] : 0xFFFFu; \
+            P = make_uint2(v0_ | (v1_ << 16), v2_ | (v3_ << 16));                              \
+        } else {                                                                               \
+            R = make_int4(-1, 0, 0, 0);                                                        \
+        }                                                                                      \
+    } while (0)
+#define CHESS_LOAD_ROW(R, C0, C1, BT)                                                          \
+    do {                                                                                       \
+        if ((R).x >= 0) {                                                                      \
+            C0 = (lane < (R).z) ? ops.bt_ci[(int64_t)(R).y + lane] : -1;                       \
+            C1 = (64 + lane < (R).z) ? ops.bt_ci[(int64_t)(R).y + 64 + lane] : -1;             \
+            if (PREF) {                                                                        \
+                const uint4 *src_ = reinterpret_cast<const uint4 *>(BtV + (int64_t)(R).y * BB); \
+                const int n16_ = (R).z * V16;                                                  \
+                _Pragma("unroll") for (int v_ = 0; v_ < RBV; ++v_) {                           \
+                    const int x_ = v_ * 64 + lane;                                             \
+                    BT[v_] = (x_ < n16_) ? src_[x_] : make_uint4(0, 0, 0, 0);                  \
+                }                                                                              \
+            }                                                                                  \
+        }                                                                                      \
+    } while (0)
+    auto pos_of = [](const uint2 &p, int i) -> unsigned {
+        const uint32_t word = (i < 2) ? p.x : p.y;
+        return (word >> ((i & 1) * 16)) & 0xFFFFu;
+    };
+
+    int jj = wave;
+    CHESS_LOAD_REC(jj, rec, pos);
+    CHESS_LOAD_ROW(rec, ci0, ci1, bt);
+    CHESS_LOAD_REC(jj + NW, recN, posN);
+    for (; jj < nj; jj += NW) {
+        const int j = rec.x;
+        // stage B for the next column, stage A for the one after
+        int ciN0 = -1, ciN1 = -1;
+        uint4 btN[RBV];
+        CHESS_LOAD_ROW(recN, ciN0, ciN1, btN);
+        int4 recNN;
+        uint2 posNN = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+        CHESS_LOAD_REC(jj + 2 * NW, recNN, posNN);
+
+        // epilogue operands of this column
+        int64_t off[NE];
+        bool valid[NE];
+        T prevv[NE];
+        double accv[NE][4];
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
-            acc[q] = (T)0;
-            outp[q] = -1;
-            if (ei[q] < c) {
-                const unsigned short op = plan.j_pos[(j0 + jj) * CMAX + ei[q]];
-                if (op != 0xFFFF) outp[q] = cbase[q] + op;
+            const unsigned op = (ei[q] < c) ? pos_of(pos, ei[q]) : 0xFFFFu;
+            valid[q] = op != 0xFFFFu;
+            off[q] = valid[q] ? (cbase[q] + op) * BB + er[q] * B + es[q] : 0;
+            prevv[q] = (valid[q] && Prev) ? Prev[off[q]] : (T)0;
+#pragma unroll
+            for (int qa = 0; qa < 4; ++qa)
+                accv[q][qa] = (valid[q] && qa < ep.nacc) ? ep.acc[qa][off[q]] : 0.0;
+        }
+
+        // this column's Bt row to LDS (prefetched through registers)
+        if (PREF) {
+            uint4 *d16 = reinterpret_cast<uint4 *>(btw);
+            const int n16 = rec.z * V16;
+#pragma unroll
+            for (int v = 0; v < RBV; ++v) {
+                const int x = v * 64 + lane;
+                if (x < n16) d16[x] = bt[v];
             }
         }
-        const int64_t s0 = ops.bt_rp[j];
-        const int64_t s1 = ops.bt_rp[j + 1];
-        for (int64_t sl = s0; sl < s1; ++sl) {
-            const int l = ops.bt_ci[sl];
-            unsigned h = hash_slot(l, plan.hcap_log2);
+        // hits of every tile row
+        int cnt[CMAX];
+#pragma unroll
+        for (int i = 0; i < CMAX; ++i) cnt[i] = 0;
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            if (kk * 64 >= rec.z) break;
+            const int l = kk == 0 ? ci0 : ci1;
             int k = -1;
-            while (true) {
-                const int key = hkey[h];
-                if (key == l) {
-                    k = hval[h];
-                    break;
+            if (l >= 0) {
+                unsigned h = hash_slot(l, plan.hcap_log2);
+                while (true) {
+                    const int key = hkey[h];
+                    if (key == l) {
+                        k = hval[h];
+                        break;
+                    }
+                    if (key < 0) break;
+                    h = (h + 1u) & hmask;
                 }
-                if (key < 0) break;
-                h = (h + 1u) & hmask;
             }
-            if (k < 0) continue;
-            const T *bb = Bt + sl * BB;
+            const int s = kk * 64 + lane;
+#pragma unroll
+            for (int i = 0; i < CMAX; ++i) {
+                if (pos_of(pos, i) == 0xFFFFu) continue;  // no output block (i, j)
+                const unsigned short pa = (k >= 0) ? upos[k * CMAX + i] : (unsigned short)0xFFFF;
+                const bool hit = pa != 0xFFFF;
+                const uint64_t m = __ballot(hit);
+                if (hit) lists[i * LS + cnt[i] + __popcll(m & lt_mask)] = ((uint32_t)s << 16) | pa;
+                cnt[i] += __popcll(m);
+            }
+        }
+        // rows longer than 128 blocks: remaining slots one round at a time
+        for (int base = 128; base < rec.z; base += 64) {
+            const int s = base + lane;
+            int k = -1;
+            if (s < rec.z) {
+                const int l = ops.bt_ci[(int64_t)rec.y + s];
+                unsigned h = hash_slot(l, plan.hcap_log2);
+                while (true) {
+                    const int key = hkey[h];
+                    if (key == l) {
+                        k = hval[h];
+                        break;
+                    }
+                    if (key < 0) break;
+                    h = (h + 1u) & hmask;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < CMAX; ++i) {
+                if (pos_of(pos, i) == 0xFFFFu) continue;
+                const unsigned short pa = (k >= 0) ? upos[k * CMAX + i] : (unsigned short)0xFFFF;
+                const bool hit = pa != 0xFFFF;
+                const uint64_t m = __ballot(hit);
+                if (hit) lists[i * LS + cnt[i] + __popcll(m & lt_mask)] = ((uint32_t)s << 16) | pa;
+                cnt[i] += __popcll(m);
+            }
+        }
+        wave_lds_sync();
+
+        T y[NE];
+        if (MFMA) {
+            const int mi = lane >> 4, grp = (lane >> 2) & 3, q = lane & 3;
+            int nmax = 0, nmine = 0;
+#pragma unroll
+            for (int i = 0; i < CMAX; ++i) {
+                nmax = max(nmax, cnt[i]);
+                if (i == mi) nmine = cnt[i];
+            }
+            const uint32_t *mylist = lists + mi * LS;
+            const float *bsrc = PREF ? reinterpret_cast<const float *>(btw)
+                                     : reinterpret_cast<const float *>(BtV) + (int64_t)rec.y * BB;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const int iters = (nmax + 3) >> 2;
+            for (int it = 0; it < iters; ++it) {
+                const int h = grp + 4 * it;
+                f32x4 a = {0.f, 0.f, 0.f, 0.f}, bb = {0.f, 0.f, 0.f, 0.f};
+                if (h < nmine) {
+                    const uint32_t e = mylist[h];
+                    a = *reinterpret_cast<const f32x4 *>(reinterpret_cast<const float *>(As) + (int)(e & 0xFFFF) * BB + q * B);
+                    bb = *reinterpret_cast<const f32x4 *>(bsrc + (int)(e >> 16) * BB + q * B);
+                }
+                acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[0], bb[0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[1], bb[1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[2], bb[2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[3], bb[3], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                acc[v] += __shfl_xor(acc[v], 4, 64);
+                acc[v] += __shfl_xor(acc[v], 8, 64);
+            }
+            float yy = acc[0];
+            if (grp == 1) yy = acc[1];
+            if (grp == 2) yy = acc[2];
+            if (grp == 3) yy = acc[3];
+            y[0] = (T)yy;
+        } else {
+            int n[NE];
+            const uint32_t *li[NE];
+            int nmax = 0;
 #pragma unroll
             for (int q = 0; q < NE; ++q) {
-                if (outp[q] >= 0) {
-                    const unsigned short pa = upos[k * CMAX + ei[q]];
-                    if (pa != 0xFFFF) {
-                        const T *a = As + (int)pa * BB + er[q] * B;
-                        const T *bs = bb + es[q] * B;
+                int nq = 0;
+#pragma unroll
+                for (int i = 0; i < CMAX; ++i)
+                    if (i == ei[q]) nq = cnt[i];
+                n[q] = valid[q] ? nq : 0;
+                li[q] = lists + (ei[q] < CMAX ? ei[q] : 0) * LS;
+                nmax = max(nmax, n[q]);
+                y[q] = (T)0;
+            }
+            const T *bsrc = PREF ? btw : BtV + (int64_t)rec.y * BB;
+            for (int h = 0; h < nmax; ++h) {
+#pragma unroll
+                for (int q = 0; q < NE; ++q) {
+                    if (h < n[q]) {
+                        const uint32_t e = li[q][h];
+                        const T *a = As + (int)(e & 0xFFFF) * BB + er[q] * B;
+                        const T *bs = bsrc + (int64_t)(e >> 16) * BB + es[q] * B;
                         T s = (T)0;
 #pragma unroll
                         for (int t = 0; t < B; ++t) s = fma(a[t], bs[t], s);
-                        acc[q] += s;
+                        y[q] += s;
                     }
                 }
             }
         }
 #pragma unroll
-        for (int q = 0; q < NE; ++q) {
-            if (outp[q] >= 0) {
-                const int64_t off = outp[q] * BB + er[q] * B + es[q];
-                T o = alpha * acc[q];
-                if (Prev) o = fma(beta, Prev[off], o);
-                Cout[off] = o;
-                const double od = (double)o;
-                for (int qa = 0; qa < ep.nacc; ++qa) ep.acc[qa][off] += ep.coef[qa] * od;
-                if (Hist) Hist[off] = o;
-                if (row0 + ei[q] == j && er[q] == es[q]) tr += od;
-            }
-        }
+        for (int q = 0; q < NE; ++q)
+            if (valid[q])
+                store_output<T>(ops, ep, off[q], y[q], prevv[q], accv[q],
+                                row0 + ei[q] == j && er[q] == es[q], tr);
+        // the next column overwrites this wave's staging and lists
+        wave_lds_sync();
+        rec = recN;
+        pos = posN;
+        ci0 = ciN0;
+        ci1 = ciN1;
+#pragma unroll
+        for (int v = 0; v < RBV; ++v) bt[v] = btN[v];
+        recN = recNN;
+        posN = posNN;
     }
+#undef CHESS_LOAD_REC
+#undef CHESS_LOAD_ROW
     if (ep.trace_partial) {
-        const double s = block_sum(tr);
+        const double s = block_sum_n<NT>(tr);
         if (threadIdx.x == 0) ep.trace_partial[tile] = s;
     }
 }
 
+// Kernel variant for (T, b, CMAX): waves per workgroup, MFMA, register prefetch.
+template <typename T, int B, int CMAX>
+struct Variant {
+    static constexpr bool MFMA = std::is_same<T, float>::value && B == 4 && CMAX == 4;
+    static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
+};
+
+template <typename T, int B, int CMAX, bool PREF>
+size_t product_lds_p(const ProductPlanDev &plan) {
+    return lds_layout<T, B, CMAX, Variant<T, B, CMAX>::NW, PREF>(plan).total;
+}
+
 template <typename T, int B, int CMAX>
 size_t product_lds(const ProductPlanDev &plan) {
-    const size_t hcap = (size_t)1 << plan.hcap_log2;
-    size_t bytes = (size_t)plan.lds_ablocks * B * B * sizeof(T) + hcap * 4 + hcap * 2 +
-                   (size_t)plan.max_u * CMAX * 2;
-    return (bytes + 15) & ~(size_t)15;
+    return (B == 4 && plan.stage_bt) ? product_lds_p<T, B, CMAX, true>(plan)
+                                     : product_lds_p<T, B, CMAX, false>(plan);
+}
+
+template <typename T, int B, int CMAX, bool PREF>
+hipError_t launch_product_p(const ProductPlanDev &plan, const ProductOperands &ops,
+                            const Epilogue &ep, hipStream_t st) {
+    constexpr int NW = Variant<T, B, CMAX>::NW;
+    constexpr bool MFMA = Variant<T, B, CMAX>::MFMA;
+    const size_t lds = product_lds_p<T, B, CMAX, PREF>(plan);
+    const void *fn = (const void *)k_product<T, B, CMAX, NW, MFMA, PREF>;
+    // raise the dynamic LDS limit once per kernel instantiation (and device
+    // ordinal), only when a launch needs more than the default 64 KB
+    static int raised_device = -1;
+    static size_t raised_to = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (lds > 65536 && (raised_device != dev || raised_to < lds)) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        raised_device = dev;
+        raised_to = lds;
+    }
+    const int nt8 = (plan.ntiles + 7) & ~7;
+    hipLaunchKernelGGL((k_product<T, B, CMAX, NW, MFMA, PREF>), dim3(nt8), dim3(64 * NW), lds, st,
+                       plan, ops, ep);
+    return hipGetLastError();
 }
 
 template <typename T, int B, int CMAX>
 hipError_t launch_product_t(const ProductPlanDev &plan, const ProductOperands &ops,
                             const Epilogue &ep, hipStream_t st) {
     if (plan.ntiles == 0) return hipSuccess;
-    const size_t lds = product_lds<T, B, CMAX>(plan);
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_masked_product<T, B, CMAX>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    if constexpr (B == 4) {
+        if (plan.stage_bt) return launch_product_p<T, B, CMAX, true>(plan, ops, ep, st);
     }
-    const int nt8 = (plan.ntiles + 7) & ~7;
-    hipLaunchKernelGGL((k_masked_product<T, B, CMAX>), dim3(nt8), dim3(kWG), lds, st, plan, ops,
-                       ep);
-    return hipGetLastError();
+    return launch_product_p<T, B, CMAX, false>(plan, ops, ep, st);
 }
 
 template <typename T, int B>

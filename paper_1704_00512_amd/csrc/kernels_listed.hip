@@ -1,0 +1,521 @@
+// The Chebyshev-step product with precomputed hit lists.
+//
+// A chain runs the same truncated product C = P_C o (A Bt^T) hundreds to
+// thousands of times on one fixed pattern triple, so every intersection
+// "which l contribute to output block (i, j)" is worked out once, on the host,
+// and stored as a compact list per (row tile, output column j, tile row i):
+// one entry per contributing l holding the block's position inside row i of A
+// and inside row j of Bt (8 + 8 bits, or 16 + 16 bits when a row has more than
+// 255 blocks).  Each step then streams these lists instead of searching.
+//
+// Work decomposition: one workgroup (NW wave64) per tile of <= CMAX
+// consecutive rows; the tile's rows of A are copied to LDS once.  Each wave
+// takes output columns j of the tile in turn.  For column j it stages row j of
+// Bt and the column's hit lists in its LDS area (both prefetched through
+// registers one column ahead, the column record two columns ahead), then
+//   MFMA (float, b = 4, CMAX = 4): v_mfma_f32_4x4x1f32 performs 16
+//     independent 4x4 outer products; slot = lane / 4 = 4 i + grp takes tile
+//     row i and every 4th hit (offset grp); lane (slot, q) supplies row q of
+//     A[i, l] as the A operand and row q of Bt[j, l] as the B operand; four
+//     MFMAs (k = t = 0..3) give the block product A[i, l] Bt[j, l]^T; the four
+//     groups of a row are summed across lanes.  Result register v is row v,
+//     lane q column q of the slot's block.
+//   VALU (float64, or b = 9): one output element (i, r, s) per lane (several
+//     for b = 9), dot products of row r of A[i, l] and row s of Bt[j, l].
+// The epilogue (kernels.h, Epilogue) is fused: 2 Y - T_{k-1}, the float64
+// weighted sums of Eq. 1, a history copy and per-tile trace partials.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace chess {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+constexpr int kEntWords = 4;  // prefetched 4-byte words of entries per lane (<= 1 KB per column)
+
+struct ListedLds {
+    size_t a, wave, wave_bt, wave_ent, total;
+};
+
+template <typename T, int B, int NW, int EW>
+__host__ __device__ inline ListedLds listed_lds(const ListedPlanDev &p) {
+    ListedLds L;
+    L.a = 0;
+    // A tile, then one block of zeros (the operand of padded MFMA slots)
+    L.wave = al16((size_t)(p.lds_ablocks + 1) * B * B * sizeof(T));
+    // Bt rows are staged only for b = 4 (16-byte chunks); b = 9 reads them from global memory
+    L.wave_bt = ((B * B * sizeof(T)) % 16 == 0)
+                    ? (((size_t)p.max_bt_row * B * B * sizeof(T) / 16 + 63) / 64) * 64 * 16
+                    : 0;
+    L.wave_ent = al16((size_t)kEntWords * 64 * 4);
+    L.total = L.wave + (size_t)NW * (L.wave_bt + L.wave_ent);
+    return L;
+}
+
+__device__ inline void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double wsum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int NT>
+__device__ inline double bsum(double v) {
+    __shared__ double red[NT / 64];
+    v = wsum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// entry decoding: position in A row i and in Bt row j
+template <int EW>
+__device__ inline void decode(const void *ent, int idx, int &pa, int &sl) {
+    if (EW == 1) {
+        const uint16_t e = reinterpret_cast<const uint16_t *>(ent)[idx];
+        pa = e & 0xFF;
+        sl = e >> 8;
+    } else {
+        const uint32_t e = reinterpret_cast<const uint32_t *>(ent)[idx];
+        pa = e & 0xFFFF;
+        sl = e >> 16;
+    }
+}
+
+template <typename T, int B, int CMAX, int NW, bool MFMA, int EW>
+__global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductOperands ops,
+                                                    Epilogue ep) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int BB = B * B;
+    constexpr int NT = 64 * NW;
+    constexpr int NE = MFMA ? 1 : (CMAX * BB + 63) / 64;
+    constexpr bool V16OK = (BB * sizeof(T)) % 16 == 0;
+    constexpr int V16 = V16OK ? (BB * (int)sizeof(T)) / 16 : 1;
+    constexpr int RBV = V16OK ? (128 * V16 + 63) / 64 : 1;  // Bt rows up to 128 blocks
+    static_assert(!MFMA || (B == 4 && CMAX == 4 && sizeof(T) == 4), "MFMA path: float, b = 4");
+
+    const int ntiles = plan.ntiles;
+    const int nt8 = (ntiles + 7) & ~7;
+    const int w = blockIdx.x;
+    // XCD-aware mapping: workgroup w runs on XCD w % 8; each XCD gets a
+    // contiguous range of tiles so neighbouring tiles share its L2.
+    const int tile = (w & 7) * (nt8 >> 3) + (w >> 3);
+    if (tile >= ntiles) return;
+    const ListedLds L = listed_lds<T, B, NW, EW>(plan);
+    const int row0 = plan.tile_row0[tile];
+    const int c = plan.tile_row0[tile + 1] - row0;
+    const int64_t ab0 = ops.a_rp[row0];
+
+    // tile rows of A -> LDS
+    T *As = reinterpret_cast<T *>(smem + L.a);
+    {
+        const int nab = (int)(ops.a_rp[row0 + c] - ab0);
+        const T *Ag = reinterpret_cast<const T *>(ops.a_val) + ab0 * BB;
+        if (V16OK) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(Ag);
+            uint4 *dst = reinterpret_cast<uint4 *>(As);
+            const int n16 = nab * V16;
+            for (int x = threadIdx.x; x < n16; x += NT) dst[x] = src[x];
+        } else {
+            for (int x = threadIdx.x; x < nab * BB; x += NT) As[x] = Ag[x];
+        }
+        for (int x = threadIdx.x; x < BB; x += NT) As[(size_t)plan.lds_ablocks * BB + x] = (T)0;
+    }
+    int rstart[CMAX];
+    int64_t cbase_i[CMAX];
+#pragma unroll
+    for (int i = 0; i < CMAX; ++i) {
+        rstart[i] = (i < c) ? (int)(ops.a_rp[row0 + i] - ab0) : 0;
+        cbase_i[i] = (i < c) ? ops.c_rp[row0 + i] : 0;
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    unsigned char *wb = smem + L.wave + (size_t)wave * (L.wave_bt + L.wave_ent);
+    T *btw = reinterpret_cast<T *>(wb);
+    unsigned char *entw = wb + L.wave_bt;
+
+    // this lane's output elements
+    int ei[NE], er[NE], es[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        if (MFMA) {
+            ei[q] = lane >> 4;
+            er[q] = (lane >> 2) & 3;
+            es[q] = lane & 3;
+        } else {
+            const int e = lane + 64 * q;
+            ei[q] = e / BB;
+            er[q] = (e % BB) / B;
+            es[q] = e % B;
+        }
+    }
+
+    const int64_t j0 = plan.j_off[tile];
+    const int nj = (int)(plan.j_off[tile + 1] - j0);
+    const int4 *recs = reinterpret_cast<const int4 *>(plan.j_rec);
+    const T *BtV = reinterpret_cast<const T *>(ops.bt_val);
+    const T *Prev = reinterpret_cast<const T *>(ep.prev);
+    const uint32_t *E32 = reinterpret_cast<const uint32_t *>(plan.entries);
+    double tr = 0.0;
+
+    // Column record (two int4): {j, Bt row start, Bt row length, first entry}
+    // and {hit counts of rows 0..3 (8 bits each), out pos rows 0|1, 2|3, 0}.
+    int4 ra = make_int4(-1, 0, 0, 0), rb = make_int4(0, -1, -1, 0);
+    int4 raN = ra, rbN = rb;
+    uint4 bt[RBV];
+    uint32_t ew[kEntWords];
+#define LREC(JJ, RA, RB)                                                              \
+    do {                                                                              \
+        if ((JJ) < nj) {                                                              \
+            RA = recs[2 * (j0 + (JJ))];                                               \
+            RB = recs[2 * (j0 + (JJ)) + 1];                                           \
+        } else {                                                                      \
+            RA = make_int4(-1, 0, 0, 0);                                              \
+        }                                                                             \
+    } while (0)
+// Row data of a column: uniform trip counts, no per-lane conditions (the
+// buffers are padded so that reading up to one 64-lane round past the end is
+// in bounds).
+#define LROW(RA, RB, BT, EWD)                                                         \
+    do {                                                                              \
+        if ((RA).x >= 0) {                                                            \
+            if (V16OK) {                                                              \
+                const uint4 *src_ = reinterpret_cast<const uint4 *>(BtV + (int64_t)(RA).y * BB) + lane; \
+                const int nv_ = ((RA).z * V16 + 63) >> 6;                             \
+                _Pragma("unroll") for (int v_ = 0; v_ < RBV; ++v_)                    \
+                    BT[v_] = (v_ < nv_) ? src_[v_ * 64] : make_uint4(0, 0, 0, 0);     \
+            }                                                                         \
+            const int tot_ = ((RB).x & 0xFF) + (((RB).x >> 8) & 0xFF) +               \
+                             (((RB).x >> 16) & 0xFF) + (((RB).x >> 24) & 0xFF);        \
+            const int nwv_ = ((tot_ * 2 * EW + 3) / 4 + 63) >> 6;                     \
+            const uint32_t *es_ = E32 + ((int64_t)(RA).w * 2 * EW) / 4 + lane;        \
+            _Pragma("unroll") for (int v_ = 0; v_ < kEntWords; ++v_)                  \
+                EWD[v_] = (v_ < nwv_) ? es_[v_ * 64] : 0u;                            \
+        }                                                                             \
+    } while (0)
+
+    // epilogue operands of a column: output offsets and the values read back
+    // (T_{k-1}, float64 accumulators)
+#define LEPI(RA, RB, OFF, VAL, PRV, ACCV)                                             \
+    do {                                                                              \
+        _Pragma("unroll") for (int q_ = 0; q_ < NE; ++q_) {                           \
+            unsigned op_ = 0xFFFFu;                                                   \
+            int64_t cb_ = 0;                                                          \
+            _Pragma("unroll") for (int i_ = 0; i_ < CMAX; ++i_) if (i_ == ei[q_]) {   \
+                const uint32_t word_ = (i_ < 2) ? (uint32_t)(RB).y : (uint32_t)(RB).z; \
+                op_ = (word_ >> ((i_ & 1) * 16)) & 0xFFFFu;                           \
+                cb_ = cbase_i[i_];                                                    \
+            }                                                                         \
+            VAL[q_] = (RA).x >= 0 && ei[q_] < c && op_ != 0xFFFFu;                    \
+            /* lanes without an output read element 0 and drop the value */          \
+            OFF[q_] = VAL[q_] ? (cb_ + op_) * BB + er[q_] * B + es[q_] : 0;           \
+            if (Prev) PRV[q_] = Prev[OFF[q_]];                                        \
+            _Pragma("unroll") for (int qa_ = 0; qa_ < 4; ++qa_)                       \
+                if (qa_ < ep.nacc) ACCV[q_][qa_] = ep.acc[qa_][OFF[q_]];             \
+        }                                                                             \
+    } while (0)
+
+    // Software pipeline: every global load is issued one column before it is
+    // used, in the order it is used (epilogue operands, Bt row and hit lists,
+    // then the record of the column after), so that the in-order completion
+    // of vector memory operations never makes a column wait for the loads of
+    // the next one.
+    // Two register sets used in turn (no copies between columns): the set of
+    // column jj holds its record, Bt row, hit lists and epilogue operands; the
+    // other set holds the record of column jj + NW.
+    struct Set {
+        int4 ra, rb;
+        uint4 bt[RBV];
+        uint32_t ew[kEntWords];
+        int64_t off[NE];
+        bool valid[NE];
+        T prev[NE];
+        double acc[NE][4];
+    };
+    Set S0, S1;
+    S0.rb = make_int4(0, -1, -1, 0);
+    S1.rb = S0.rb;
+    auto column = [&](Set &C, Set &N, int JJ) __attribute__((always_inline)) {
+        // loads for column JJ + NW (into N), then the record of JJ + 2 NW (into C)
+        LEPI(N.ra, N.rb, N.off, N.valid, N.prev, N.acc);
+        LROW(N.ra, N.rb, N.bt, N.ew);
+        const int jc = C.ra.x, rowc = C.ra.y, nslc = C.ra.z, rbx = C.rb.x;
+        (void)rowc;
+        (void)nslc;
+        LREC(JJ + 2 * NW, C.ra, C.rb);
+        int cnt[CMAX], eoff[CMAX];
+        {
+            int acc_off = 0;
+#pragma unroll
+            for (int i = 0; i < CMAX; ++i) {
+                cnt[i] = (rbx >> (8 * i)) & 0xFF;
+                eoff[i] = acc_off;
+                acc_off += cnt[i];
+            }
+        }
+        // stage this column's Bt row and hit lists in the wave's LDS area
+        const T *bsrc;
+        if (V16OK) {
+            uint4 *d16 = reinterpret_cast<uint4 *>(btw) + lane;
+            const int nv = (nslc * V16 + 63) >> 6;
+#pragma unroll
+            for (int v = 0; v < RBV; ++v)
+                if (v < nv) d16[v * 64] = C.bt[v];
+            bsrc = btw;
+        } else {
+            bsrc = BtV + (int64_t)rowc * BB;
+        }
+        {
+            uint32_t *e32 = reinterpret_cast<uint32_t *>(entw) + lane;
+            const int tot = cnt[0] + (CMAX > 1 ? cnt[1 % CMAX] : 0) + (CMAX > 2 ? cnt[2 % CMAX] : 0) +
+                            (CMAX > 3 ? cnt[3 % CMAX] : 0);
+            const int nwv = ((tot * 2 * EW + 3) / 4 + 63) >> 6;
+#pragma unroll
+            for (int v = 0; v < kEntWords; ++v)
+                if (v < nwv) e32[v * 64] = C.ew[v];
+        }
+        wave_sync_lds();
+
+        T y[NE];
+        if (MFMA) {
+            // Branch-free loop: slots past the end of their row's list read the
+            // zero block, so every lane issues the same instructions.
+            const int mi = lane >> 4, grp = (lane >> 2) & 3, q = lane & 3;
+            int nmax = 0, nmine = 0, omine = 0, rs = 0;
+#pragma unroll
+            for (int i = 0; i < CMAX; ++i) {
+                nmax = max(nmax, cnt[i]);
+                if (i == mi) {
+                    nmine = cnt[i];
+                    omine = eoff[i];
+                    rs = rstart[i];
+                }
+            }
+            nmax = __builtin_amdgcn_readfirstlane(nmax);
+            typedef __attribute__((address_space(3))) const unsigned char lds_u8;
+            typedef __attribute__((address_space(3))) const f32x4 lds_f4;
+            lds_u8 *zp = (lds_u8 *)(As + (size_t)plan.lds_ablocks * BB);
+            lds_u8 *a_base = (lds_u8 *)(As + rs * BB) + q * 16;
+            lds_u8 *b_base = (lds_u8 *)bsrc + q * 16;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const int iters = (nmax + 3) >> 2;
+            // operand addresses of hit h of this slot (zero block past the list)
+            auto addr = [&](int hh, lds_u8 *&ap, lds_u8 *&bp) {
+                uint32_t pa, sl;
+                if constexpr (EW == 1) {
+                    const uint32_t e = reinterpret_cast<const uint16_t *>(entw)[omine + hh];
+                    pa = e & 0xFFu;
+                    sl = e >> 8;
+                } else {
+                    const uint32_t e = reinterpret_cast<const uint32_t *>(entw)[omine + hh];
+                    pa = e & 0xFFFFu;
+                    sl = e >> 16;
+                }
+                const bool ok = hh < nmine;
+                ap = ok ? a_base + (pa << 6) : zp;
+                bp = ok ? b_base + (sl << 6) : zp;
+            };
+            int it = 0;
+            // four hits per slot at a time: all LDS reads issued before the MFMAs
+            for (; it + 4 <= iters; it += 4) {
+                lds_u8 *ap[4], *bp[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) addr(grp + 4 * (it + u), ap[u], bp[u]);
+                f32x4 a[4], bb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = *(lds_f4 *)ap[u];
+                    bb[u] = *(lds_f4 *)bp[u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][0], bb[u][0], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][1], bb[u][1], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][2], bb[u][2], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][3], bb[u][3], acc, 0, 0, 0);
+                }
+            }
+            for (; it < iters; ++it) {
+                lds_u8 *ap, *bp;
+                addr(grp + 4 * it, ap, bp);
+                const f32x4 a = *(lds_f4 *)ap;
+                const f32x4 bb = *(lds_f4 *)bp;
+                acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[0], bb[0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[1], bb[1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[2], bb[2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[3], bb[3], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                acc[v] += __shfl_xor(acc[v], 4, 64);
+                acc[v] += __shfl_xor(acc[v], 8, 64);
+            }
+            float yy = acc[0];
+            if (grp == 1) yy = acc[1];
+            if (grp == 2) yy = acc[2];
+            if (grp == 3) yy = acc[3];
+            y[0] = (T)yy;
+        } else {
+            int n[NE], o[NE], rsq[NE];
+            int nmax = 0;
+#pragma unroll
+            for (int q = 0; q < NE; ++q) {
+                n[q] = 0;
+                o[q] = 0;
+                rsq[q] = 0;
+#pragma unroll
+                for (int i = 0; i < CMAX; ++i)
+                    if (i == ei[q]) {
+                        n[q] = cnt[i];
+                        o[q] = eoff[i];
+                        rsq[q] = rstart[i];
+                    }
+                if (!C.valid[q]) n[q] = 0;
+                nmax = max(nmax, n[q]);
+                y[q] = (T)0;
+            }
+            for (int h = 0; h < nmax; ++h) {
+#pragma unroll
+                for (int q = 0; q < NE; ++q) {
+                    if (h < n[q]) {
+                        int pa, sl;
+                        decode<EW>(entw, o[q] + h, pa, sl);
+                        const T *a = As + (rsq[q] + pa) * BB + er[q] * B;
+                        const T *bs = bsrc + (int64_t)sl * BB + es[q] * B;
+                        T s = (T)0;
+#pragma unroll
+                        for (int t = 0; t < B; ++t) s = fma(a[t], bs[t], s);
+                        y[q] += s;
+                    }
+                }
+            }
+        }
+        // fused epilogue
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            if (!C.valid[q]) continue;
+            T o = (T)ep.alpha * y[q];
+            if (Prev) o = fma((T)ep.beta, C.prev[q], o);
+            reinterpret_cast<T *>(ops.c_out)[C.off[q]] = o;
+            const double od = (double)o;
+#pragma unroll
+            for (int qa = 0; qa < 4; ++qa)
+                if (qa < ep.nacc) ep.acc[qa][C.off[q]] = C.acc[q][qa] + ep.coef[qa] * od;
+            if (ep.hist) reinterpret_cast<T *>(ep.hist)[C.off[q]] = o;
+            if (row0 + ei[q] == jc && er[q] == es[q]) tr += od;
+        }
+        wave_sync_lds();
+    };
+    int jj = wave;
+    LREC(jj, S0.ra, S0.rb);
+    LEPI(S0.ra, S0.rb, S0.off, S0.valid, S0.prev, S0.acc);
+    LROW(S0.ra, S0.rb, S0.bt, S0.ew);
+    LREC(jj + NW, S1.ra, S1.rb);
+    for (; jj < nj; jj += 2 * NW) {
+        column(S0, S1, jj);
+        if (jj + NW >= nj) break;
+        column(S1, S0, jj + NW);
+    }
+#undef LEPI
+#undef LREC
+#undef LROW
+    if (ep.trace_partial) {
+        const double s = bsum<NT>(tr);
+        if (threadIdx.x == 0) ep.trace_partial[tile] = s;
+    }
+}
+
+template <typename T, int B, int CMAX>
+struct LVariant {
+    static constexpr bool MFMA = std::is_same<T, float>::value && B == 4 && CMAX == 4;
+    static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
+};
+
+template <typename T, int B, int CMAX, int EW>
+hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                    hipStream_t st, size_t *lds_out) {
+    constexpr int NW = LVariant<T, B, CMAX>::NW;
+    constexpr bool MFMA = LVariant<T, B, CMAX>::MFMA;
+    const size_t lds = listed_lds<T, B, NW, EW>(plan).total;
+    if (lds_out) {
+        *lds_out = lds;
+        return hipSuccess;
+    }
+    if (plan.ntiles == 0) return hipSuccess;
+    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MFMA, EW>;
+    static int raised_device = -1;
+    static size_t raised_to = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (lds > 65536 && (raised_device != dev || raised_to < lds)) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        raised_device = dev;
+        raised_to = lds;
+    }
+    const int nt8 = (plan.ntiles + 7) & ~7;
+    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MFMA, EW>), dim3(nt8), dim3(64 * NW), lds, st,
+                       plan, ops, ep);
+    return hipGetLastError();
+}
+
+template <typename T, int B, int CMAX>
+hipError_t launch_lc(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                     hipStream_t st, size_t *lds_out) {
+    if (plan.entry_width == 1) return launch_l<T, B, CMAX, 1>(plan, ops, ep, st, lds_out);
+    if (plan.entry_width == 2) return launch_l<T, B, CMAX, 2>(plan, ops, ep, st, lds_out);
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int B>
+hipError_t launch_lb(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                     hipStream_t st, size_t *lds_out) {
+    switch (plan.cmax) {
+        case 1: return launch_lc<T, B, 1>(plan, ops, ep, st, lds_out);
+        case 2: return launch_lc<T, B, 2>(plan, ops, ep, st, lds_out);
+        case 4: return launch_lc<T, B, 4>(plan, ops, ep, st, lds_out);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t dispatch_listed(int dtype, int b, const ListedPlanDev &plan, const ProductOperands &ops,
+                           const Epilogue &ep, hipStream_t st, size_t *lds_out) {
+    if (dtype == 0 && b == 4) return launch_lb<double, 4>(plan, ops, ep, st, lds_out);
+    if (dtype == 0 && b == 9) return launch_lb<double, 9>(plan, ops, ep, st, lds_out);
+    if (dtype == 1 && b == 4) return launch_lb<float, 4>(plan, ops, ep, st, lds_out);
+    if (dtype == 1 && b == 9) return launch_lb<float, 9>(plan, ops, ep, st, lds_out);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
+                                 const ProductOperands &ops, const Epilogue &ep, hipStream_t st) {
+    return dispatch_listed(dtype, b, plan, ops, ep, st, nullptr);
+}
+
+size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan) {
+    size_t lds = 0;
+    if (dispatch_listed(dtype, b, plan, ProductOperands{}, Epilogue{}, nullptr, &lds) != hipSuccess)
+        return (size_t)-1;
+    return lds;
+}
+
+}  // namespace chess
