@@ -97,17 +97,20 @@ __device__ inline void decode(const void *ent, int idx, int &pa, int &sl) {
     }
 }
 
-template <typename T, int B, int CMAX, int NW, bool MFMA, int EW>
+template <typename T, int B, int CMAX, int NW, int MODE, int EW>
 __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductOperands ops,
                                                     Epilogue ep) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int BB = B * B;
     constexpr int NT = 64 * NW;
-    constexpr int NE = MFMA ? 1 : (CMAX * BB + 63) / 64;
+    constexpr bool MFMA = MODE == 1;
+    constexpr bool MF64 = MODE == 2;
+    constexpr int NE = (MFMA || MF64) ? 1 : (CMAX * BB + 63) / 64;
     constexpr bool V16OK = (BB * sizeof(T)) % 16 == 0;
     constexpr int V16 = V16OK ? (BB * (int)sizeof(T)) / 16 : 1;
     constexpr int RBV = V16OK ? (128 * V16 + 63) / 64 : 1;  // Bt rows up to 128 blocks
     static_assert(!MFMA || (B == 4 && CMAX == 4 && sizeof(T) == 4), "MFMA path: float, b = 4");
+    static_assert(!MF64 || (B == 4 && CMAX == 4 && sizeof(T) == 8), "MFMA64 path: double, b = 4");
 
     const int ntiles = plan.ntiles;
     const int nt8 = (ntiles + 7) & ~7;
@@ -145,7 +148,9 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     }
     __syncthreads();
 
-    const int wave = threadIdx.x >> 6;
+    // the wave index is uniform: keep it (and everything derived from the
+    // column records) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     unsigned char *wb = smem + L.wave + (size_t)wave * (L.wave_bt + L.wave_ent);
     T *btw = reinterpret_cast<T *>(wb);
@@ -158,6 +163,11 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
         if (MFMA) {
             ei[q] = lane >> 4;
             er[q] = (lane >> 2) & 3;
+            es[q] = lane & 3;
+        } else if (MF64) {
+            // v_mfma_f64_4x4x4f64 result: lane 16 r + 4 blk + s holds D[blk][r][s]
+            ei[q] = (lane >> 2) & 3;
+            er[q] = lane >> 4;
             es[q] = lane & 3;
         } else {
             const int e = lane + 64 * q;
@@ -372,6 +382,67 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             if (grp == 2) yy = acc[2];
             if (grp == 3) yy = acc[3];
             y[0] = (T)yy;
+        } else if (MF64) {
+            // v_mfma_f64_4x4x4f64 runs 4 independent 4x4x4 block products:
+            // block blk = tile row; operand lane 16 t + 4 blk + x holds
+            // A[blk][x][t] (row x of A[i, l], column t) and B[blk][t][x]
+            // (= Bt[j, l][x][t]); one hit of every row per instruction, rows
+            // past the end of their list read the zero block.
+            const int blk = (lane >> 2) & 3;
+            const int x = lane & 3, t = lane >> 4;
+            int nmax = 0, nmine = 0, omine = 0, rs = 0;
+#pragma unroll
+            for (int i = 0; i < CMAX; ++i) {
+                nmax = max(nmax, cnt[i]);
+                if (i == blk) {
+                    nmine = cnt[i];
+                    omine = eoff[i];
+                    rs = rstart[i];
+                }
+            }
+            nmax = __builtin_amdgcn_readfirstlane(nmax);
+            typedef __attribute__((address_space(3))) const unsigned char lds_u8;
+            typedef __attribute__((address_space(3))) const double lds_d;
+            lds_u8 *zp = (lds_u8 *)(As + (size_t)plan.lds_ablocks * BB);
+            const int eoffb = (x * 4 + t) * 8;
+            lds_u8 *a_base = (lds_u8 *)(As + rs * BB) + eoffb;
+            lds_u8 *b_base = (lds_u8 *)bsrc + eoffb;
+            double acc = 0.0;
+            auto addr = [&](int hh, lds_u8 *&ap, lds_u8 *&bp) {
+                uint32_t pa, sl;
+                if constexpr (EW == 1) {
+                    const uint32_t e = reinterpret_cast<const uint16_t *>(entw)[omine + hh];
+                    pa = e & 0xFFu;
+                    sl = e >> 8;
+                } else {
+                    const uint32_t e = reinterpret_cast<const uint32_t *>(entw)[omine + hh];
+                    pa = e & 0xFFFFu;
+                    sl = e >> 16;
+                }
+                const bool ok = hh < nmine;
+                ap = ok ? a_base + (pa << 7) : zp;
+                bp = ok ? b_base + (sl << 7) : zp;
+            };
+            int h = 0;
+            for (; h + 4 <= nmax; h += 4) {
+                lds_u8 *ap[4], *bp[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) addr(h + u, ap[u], bp[u]);
+                double a[4], bb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = *(lds_d *)ap[u];
+                    bb[u] = *(lds_d *)bp[u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u], bb[u], acc, 0, 0, 0);
+            }
+            for (; h < nmax; ++h) {
+                lds_u8 *ap, *bp;
+                addr(h, ap, bp);
+                acc = __builtin_amdgcn_mfma_f64_4x4x4f64(*(lds_d *)ap, *(lds_d *)bp, acc, 0, 0, 0);
+            }
+            y[0] = (T)acc;
         } else {
             int n[NE], o[NE], rsq[NE];
             int nmax = 0;
@@ -444,7 +515,8 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
 
 template <typename T, int B, int CMAX>
 struct LVariant {
-    static constexpr bool MFMA = std::is_same<T, float>::value && B == 4 && CMAX == 4;
+    // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
+    static constexpr int MODE = (B == 4 && CMAX == 4) ? (std::is_same<T, float>::value ? 1 : 2) : 0;
     static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
 };
 
@@ -452,14 +524,14 @@ template <typename T, int B, int CMAX, int EW>
 hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
                     hipStream_t st, size_t *lds_out) {
     constexpr int NW = LVariant<T, B, CMAX>::NW;
-    constexpr bool MFMA = LVariant<T, B, CMAX>::MFMA;
+    constexpr int MODE = LVariant<T, B, CMAX>::MODE;
     const size_t lds = listed_lds<T, B, NW, EW>(plan).total;
     if (lds_out) {
         *lds_out = lds;
         return hipSuccess;
     }
     if (plan.ntiles == 0) return hipSuccess;
-    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MFMA, EW>;
+    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW>;
     static int raised_device = -1;
     static size_t raised_to = 0;
     int dev = 0;
@@ -471,7 +543,7 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
         raised_to = lds;
     }
     const int nt8 = (plan.ntiles + 7) & ~7;
-    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MFMA, EW>), dim3(nt8), dim3(64 * NW), lds, st,
+    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW>), dim3(nt8), dim3(64 * NW), lds, st,
                        plan, ops, ep);
     return hipGetLastError();
 }
