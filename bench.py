@@ -70,7 +70,7 @@ def count_triples(sysm):
 
 def kernel_source_hash():
     h = hashlib.sha1()
-    for f in ("kernels.hip", "kernels.h"):
+    for f in ("kernels.hip", "kernels_listed.hip", "kernels.h"):
         h.update(open(os.path.join(ROOT, "paper_1704_00512_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:12]
 
@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--workload", default="large80k")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the multi-GPU column-slab sharding is a design "
@@ -135,6 +137,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = 1 << 28  # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for i in range(5):
+            torch.neg(src, out=dst)  # an ordinary elementwise kernel, not a DMA copy
+            torch.cuda.synchronize()
+            log(f"copy {i}: {n * 4} bytes")
+        return
 
     from paper_1704_00512_amd import BlockPattern, Context, chess_fermi_operator
     from workloads.generator import CONFIGS, make_config
@@ -201,7 +213,7 @@ def main():
     else:
         roof = dict(bound="alu", achieved=round(tflops, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(tflops / FP32_PEAK_TFLOPS, 4))
-    roof.update(traffic=traffic, kernel="k_masked_product<float,4,4>",
+    roof.update(traffic=traffic, kernel="k_listed<float,4,4,...> (chain product)",
                 avg_launch_ms=round(avg_launch_ms, 4),
                 algorithmic_bytes_per_call=int(bytes_call), launches_per_call=launches_call,
                 flops_per_launch=flops_launch, achieved_gbs=round(gbs, 1),
@@ -221,12 +233,18 @@ def main():
                roofline=roof)
 
     if not args.no_plain:
-        log("plain float64 form (Gershgorin bounds, two passes)")
+        log("plain float64 form (Gershgorin bounds, two passes, same tol_fit)")
+        # the chain reports its own progress; the stream waits it adds are
+        # one per 512 products, well under 0.1 % of the chain time
+        ctx.set_progress(lambda stage, done, total: log(f"  plain f64 {stage}: {done}/{total}"),
+                         every=512)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, pinfo = run(dict(precision="f64", bounds_mode="gershgorin", store_history=0))
+        _, pinfo = run(dict(precision="f64", bounds_mode="gershgorin", store_history=0,
+                            tol_fit=fast["tol_fit"], tol_fit_s=fast["tol_fit_s"]))
         torch.cuda.synchronize()
         tp = (time.perf_counter() - t0) * 1e3
+        ctx.set_progress(None)
         K_plain = K.cpu().numpy()
         diff = float(np.max(np.abs(K_plain - K_fast)))
         out["plain_f64"] = dict(ms=round(tp, 1), n_pl=pinfo["n_pl"], passes=pinfo["passes"],

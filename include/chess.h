@@ -127,6 +127,9 @@ typedef struct {
     int32_t chain_steps;  /* products launched in chains (all matrices) */
     double ms_total, ms_setup, ms_s_chain, ms_transform, ms_h_chain, ms_mu, ms_post;
     double ms_chain_kernel; /* summed device time of the H~' chain product kernel */
+    int32_t kernel_variant; /* variant of the chain product kernel chosen by timing, or
+                               forced by CHESS_LISTED_VARIANT in the environment
+                               (-1: the searching kernel) */
 } chess_info;
 
 /* Fills *opts with the defaults listed above. */
@@ -136,6 +139,19 @@ void chess_default_opts(chess_opts *opts);
  * (a hipStream_t; NULL = the null stream). */
 int chess_create(chess_ctx **ctx, int device, void *hip_stream);
 int chess_destroy(chess_ctx *ctx);
+/*
+ * Progress report from inside a chain: after every `every` products of a
+ * chain the library waits for the stream and calls fn(user, stage, done,
+ * total), with stage a static string naming the chain ("S chain", "H chain",
+ * "H chain (accumulate)", ...), done the number of terms formed and total
+ * the chain length n_pl. fn runs on the calling thread and must not call
+ * back into the library. fn = NULL switches reporting off. Returns
+ * CHESS_E_ARG for a NULL ctx or for every <= 0 with a non-NULL fn. The extra
+ * waits cost one stream synchronisation per `every` products.
+ */
+typedef void (*chess_progress_fn)(void *user, const char *stage, int64_t done, int64_t total);
+int chess_set_progress(chess_ctx *ctx, chess_progress_fn fn, void *user, int32_t every);
+
 /* Message for the last non-zero return on this context (never NULL). */
 const char *chess_last_error(const chess_ctx *ctx);
 

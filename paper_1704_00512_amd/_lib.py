@@ -55,7 +55,8 @@ class chess_info(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("ms_setup", ctypes.c_double),
                 ("ms_s_chain", ctypes.c_double), ("ms_transform", ctypes.c_double),
                 ("ms_h_chain", ctypes.c_double), ("ms_mu", ctypes.c_double),
-                ("ms_post", ctypes.c_double), ("ms_chain_kernel", ctypes.c_double)]
+                ("ms_post", ctypes.c_double), ("ms_chain_kernel", ctypes.c_double),
+                ("kernel_variant", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -63,7 +64,10 @@ class chess_info(ctypes.Structure):
 
 EXPORTS = ["chess_default_opts", "chess_create", "chess_destroy", "chess_last_error",
            "chess_fermi_operator", "chess_matrix_power", "chess_eigs_in_interval",
-           "chess_chebyshev", "chess_masked_product"]
+           "chess_chebyshev", "chess_masked_product", "chess_set_progress"]
+
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64,
+                               ctypes.c_int64)
 
 _lib = None
 
@@ -98,6 +102,7 @@ def load():
                                   P(ctypes.c_double), P(chess_matrix), P(ctypes.c_double),
                                   P(chess_opts)]
     L.chess_masked_product.argtypes = [vp, P(chess_matrix), P(chess_matrix), P(chess_matrix)]
+    L.chess_set_progress.argtypes = [vp, PROGRESS_FN, vp, ctypes.c_int32]
     for name in EXPORTS:
         if name not in ("chess_default_opts", "chess_last_error"):
             getattr(L, name).restype = ctypes.c_int

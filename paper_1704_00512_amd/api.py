@@ -113,6 +113,20 @@ class Context:
         if rc != 0:
             raise ChessError(rc, self._L.chess_last_error(self._h).decode())
 
+    def set_progress(self, fn, every: int = 256):
+        """Calls fn(stage: str, done: int, total: int) every `every` chain
+        products (after a stream wait); fn=None switches it off."""
+        if fn is None:
+            self._progress = None
+            self._check(self._L.chess_set_progress(self._h, _lib.PROGRESS_FN(), None, 0))
+            return
+
+        def trampoline(_user, stage, done, total):
+            fn(stage.decode(), int(done), int(total))
+
+        self._progress = _lib.PROGRESS_FN(trampoline)  # kept alive with the context
+        self._check(self._L.chess_set_progress(self._h, self._progress, None, int(every)))
+
 
 def chess_fermi_operator(ctx: Context, H: torch.Tensor, pat_h: BlockPattern, S: torch.Tensor,
                          pat_s: BlockPattern, pattern: BlockPattern, n_electrons: float,

@@ -139,6 +139,7 @@ struct ListedPlan {
     const Pattern *a = nullptr, *bt = nullptr, *c = nullptr;
     int dtype = 0;
     bool usable = false;  // false: rows too long for the list format
+    int tuned_variant = -1;  // fastest kernel variant on this plan (-1: not timed yet)
     ListedPlanDev dev;
     DevBuf d_tile_row0, d_j_off, d_j_rec, d_entries;
 };
@@ -153,6 +154,9 @@ struct chess_ctx {
     std::vector<std::unique_ptr<chess::EmbedMap>> embeds;
     std::vector<std::unique_ptr<chess::ProductPlan>> plans;
     std::vector<std::unique_ptr<chess::ListedPlan>> lplans;
+    chess_progress_fn progress = nullptr;
+    void *progress_user = nullptr;
+    int32_t progress_every = 0;
 };
 
 namespace chess {
@@ -369,8 +373,8 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
 // ListedPlanDev).  The intersections of sorted rows are computed once here, in
 // parallel over tiles.  Returns a plan with usable = false when a row is too
 // long for the list format; callers then use the searching kernel.
-static const ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Pattern *Bt,
-                                         const Pattern *C, int dtype) {
+static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Pattern *Bt,
+                                   const Pattern *C, int dtype) {
     for (auto &e : ctx->lplans)
         if (e->a == A && e->bt == Bt && e->c == C && e->dtype == dtype) return e.get();
     auto P = std::make_unique<ListedPlan>();
@@ -688,8 +692,69 @@ struct ChainRequest {
     int dtype = 0;
     void *hist = nullptr;  // optional device [n_pl][nnzK*b*b] in dtype
     std::vector<double> *moments = nullptr;
+    const char *label = "chain";  // stage name given to the progress callback
     double kernel_ms = 0.0;  // out: device time of the product launches
+    int variant = -1;        // out: kernel variant of the listed product (-1: searching kernel)
 };
+
+// Kernel variant of a listed plan.  CHESS_LISTED_VARIANT=<v> in the
+// environment forces variant v; otherwise the first chain long enough to pay
+// for it times every variant on its own operands (one warm-up and three timed
+// launches each, written to a scratch output) and the fastest one is kept for
+// the plan's lifetime.
+static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int n_pl,
+                                  const void *a, const void *bt, const void *prev) {
+    const int b = lp->a->b;
+    const int nvar = listed_product_variants(dtype, b, lp->dev);
+    if (const char *env = std::getenv("CHESS_LISTED_VARIANT")) {
+        char *end = nullptr;
+        const long v = std::strtol(env, &end, 10);
+        if (end == env || v < 0 || v >= nvar)
+            CHESS_THROW(CHESS_E_ARG, "CHESS_LISTED_VARIANT=%s: expected 0..%d", env, nvar - 1);
+        lp->dev.variant = (int)v;
+        if (listed_product_lds_bytes(dtype, b, lp->dev) > 160 * 1024)
+            CHESS_THROW(CHESS_E_UNSUPPORTED, "kernel variant %ld needs more than 160 KB of LDS", v);
+        return;
+    }
+    if (lp->tuned_variant >= 0) {
+        lp->dev.variant = lp->tuned_variant;
+        return;
+    }
+    lp->dev.variant = 0;
+    if (nvar == 1 || n_pl < 64) return;  // too short a chain to time variants on
+    hipStream_t st = ctx->stream;
+    DevBuf out(vbytes(lp->c, dtype));
+    ProductOperands ops;
+    ops.a_rp = lp->a->d_rp.as<int64_t>();
+    ops.a_val = a;
+    ops.bt_rp = lp->bt->d_rp.as<int64_t>();
+    ops.bt_ci = lp->bt->d_ci.as<int32_t>();
+    ops.bt_val = bt;
+    ops.c_rp = lp->c->d_rp.as<int64_t>();
+    ops.c_out = out.p;
+    Epilogue ep;
+    ep.alpha = 2.0;
+    ep.beta = -1.0;
+    ep.prev = prev;
+    Timer tm(st);
+    double best = 0.0;
+    int best_v = 0;
+    for (int v = 0; v < nvar; ++v) {
+        ListedPlanDev d = lp->dev;
+        d.variant = v;
+        if (listed_product_lds_bytes(dtype, b, d) > 160 * 1024) continue;
+        HIPCHECK(launch_listed_product(dtype, b, d, ops, ep, st));
+        tm.start();
+        for (int r = 0; r < 3; ++r) HIPCHECK(launch_listed_product(dtype, b, d, ops, ep, st));
+        const double ms = tm.stop();
+        if (v == 0 || ms < best) {
+            best = ms;
+            best_v = v;
+        }
+    }
+    lp->tuned_variant = best_v;
+    lp->dev.variant = best_v;
+}
 
 // Runs T_0 .. T_{n_pl-1} in transposed storage U_k = T_k^T (see kernels.hip).
 static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
@@ -699,7 +764,7 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     const int dtype = rq.dtype;
     const int64_t nK = PK->nnzb * b * b;
     const EmbedMap *emb = get_embed(ctx, PM, PK, "M~ in the chain pattern");
-    const ListedPlan *lplan = get_listed_plan(ctx, PK, PM, PK, dtype);
+    ListedPlan *lplan = get_listed_plan(ctx, PK, PM, PK, dtype);
     const ProductPlan *plan = lplan->usable ? nullptr : get_plan(ctx, PK, PM, PK, dtype);
     const size_t tb = vbytes(PK, dtype);
     // Bt gets 16 KB of slack: the listed kernel reads whole 64-lane rounds of a row
@@ -711,6 +776,10 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     HIPCHECK(launch_zero(U1.p, tb, st));
     if (rq.n_pl > 1)
         HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, emb->d_map_t.as<int64_t>(), rq.Mt, U1.p, 1, st));
+    if (lplan->usable) {
+        select_listed_variant(ctx, lplan, dtype, rq.n_pl, U1.p, Bt.p, U0.p);
+        rq.variant = lplan->dev.variant;
+    }
     for (int q = 0; q < rq.nq; ++q) {
         const double *c = rq.coef + (size_t)q * rq.n_pl;
         HIPCHECK(launch_axpby_to_f64(dtype, nK, 0.5 * c[0], U0.p, rq.n_pl > 1 ? c[1] : 0.0, U1.p, rq.acc[q], st));
@@ -753,6 +822,10 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
         else
             product(ctx, dtype, plan, ucur, Bt.p, uprev, ep);
         std::swap(ucur, uprev);
+        if (ctx->progress && (k + 1) % ctx->progress_every == 0) {
+            HIPCHECK(hipStreamSynchronize(st));
+            ctx->progress(ctx->progress_user, rq.label, k + 1, rq.n_pl);
+        }
     }
     rq.kernel_ms = tm.stop();
     if (rq.n_pl > 2)
@@ -825,6 +898,7 @@ struct PowerResult {
     int n_pl;
     int reexp;
     double kernel_ms;
+    int variant = -1;
 };
 
 static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *S,
@@ -855,6 +929,7 @@ static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *
         }
         std::vector<double> mom;
         ChainRequest rq;
+        rq.label = "S chain";
         rq.PM = PS;
         rq.Mt = St.as<double>();
         rq.PK = PK;
@@ -867,6 +942,7 @@ static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *
         run_chain(ctx, rq);
         r.n_pl = n_pl;
         r.kernel_ms += rq.kernel_ms;
+        r.variant = rq.variant;
         if (growth_ok(mom, PK->n())) break;
         if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "spectral bounds [%g, %g] still fail the growth test", r.lo, r.hi);
         // widen both sides by 10% of the width (the lower bound stays positive)
@@ -973,6 +1049,7 @@ static void fill_info_defaults(chess_info *info) {
     const double nan = std::numeric_limits<double>::quiet_NaN();
     info->mu = info->lo = info->hi = info->s_lo = info->s_hi = nan;
     info->tr_ks = info->ne_chain = info->penalty = nan;
+    info->kernel_variant = -1;
 }
 
 static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
@@ -1012,6 +1089,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     int n_pl = 0, reexp = 0, passes = 0;
     double penalty = std::numeric_limits<double>::quiet_NaN();
     double ms_chain = 0.0, kernel_ms = 0.0;
+    int variant = -1;
     bool have_hist = false;
     Timer tm(st);
     for (int attempt = 0;; ++attempt) {
@@ -1039,6 +1117,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         }
         tm.start();
         ChainRequest rq;
+        rq.label = "H chain";
         rq.PM = PH;
         rq.Mt = Ht.as<double>();
         rq.PK = PK;
@@ -1057,6 +1136,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         run_chain(ctx, rq);
         ms_chain += tm.stop();
         kernel_ms += rq.kernel_ms;
+        variant = rq.variant;
         passes++;
         double fit_err = 1.0;
         penalty = hostmath::penalty_trace(mom, -200.0, &fit_err);
@@ -1111,6 +1191,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
             HIPCHECK(hipStreamSynchronize(st));
         } else {
             ChainRequest rq;
+            rq.label = "H chain (accumulate)";
             rq.PM = PH;
             rq.Mt = Ht.as<double>();
             rq.PK = PK;
@@ -1121,6 +1202,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
             rq.acc[0] = accK.as<double>();
             run_chain(ctx, rq);
             kernel_ms += rq.kernel_ms;
+            variant = rq.variant;
             passes++;
         }
         ms_chain += tm.stop();
@@ -1153,6 +1235,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         info->ms_mu = ms_mu;
         info->ms_post = t_end - t_post0;
         info->ms_chain_kernel = kernel_ms;
+        info->kernel_variant = variant;
     }
 }
 
@@ -1186,6 +1269,7 @@ static void matrix_power(chess_ctx *ctx, const chess_matrix *S, double a,
         info->chain_steps = std::max(r.n_pl - 2, 0);
         info->ms_total = now_ms() - t0;
         info->ms_chain_kernel = r.kernel_ms;
+        info->kernel_variant = r.variant;
     }
 }
 
@@ -1212,7 +1296,7 @@ static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_
     const int b = PK->b;
     DevBuf Ht(sizeof(double) * (size_t)PH->nnzb * b * b);
     std::vector<double> mom;
-    int n_pl = 0, reexp = 0;
+    int n_pl = 0, reexp = 0, variant = -1;
     double kernel_ms = 0;
     for (int attempt = 0;; ++attempt) {
         double sigma, tau;
@@ -1224,6 +1308,7 @@ static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_
         }
         HIPCHECK(launch_scale_shift(b, PH->nnzb, PH->d_brow.as<int32_t>(), PH->d_ci.as<int32_t>(), F.Hp.as<double>(), Ht.as<double>(), sigma, tau, ctx->stream));
         ChainRequest rq;
+        rq.label = "eigenvalue chain";
         rq.PM = PH;
         rq.Mt = Ht.as<double>();
         rq.PK = PK;
@@ -1232,6 +1317,7 @@ static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_
         rq.moments = &mom;
         run_chain(ctx, rq);
         kernel_ms += rq.kernel_ms;
+        variant = rq.variant;
         if (growth_ok(mom, PK->n())) break;
         if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "bounds [%g, %g] fail the growth test", lo, hi);
         const double w = hi - lo;
@@ -1257,6 +1343,7 @@ static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_
         info->reexpansions = reexp;
         info->ms_total = now_ms() - t0;
         info->ms_chain_kernel = kernel_ms;
+        info->kernel_variant = variant;
     }
 }
 
@@ -1285,6 +1372,7 @@ static void chebyshev(chess_ctx *ctx, const chess_matrix *M, double lo, double h
     HIPCHECK(launch_scale_shift(b, PM->nnzb, PM->d_brow.as<int32_t>(), PM->d_ci.as<int32_t>(), (const double *)M->val, Mt.as<double>(), sigma, tau, st));
     std::vector<std::unique_ptr<DevBuf>> accs;
     ChainRequest rq;
+    rq.label = "chebyshev chain";
     rq.PM = PM;
     rq.Mt = Mt.as<double>();
     rq.PK = PK;
@@ -1386,6 +1474,18 @@ int chess_destroy(chess_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     delete ctx;
+    return CHESS_OK;
+}
+
+int chess_set_progress(chess_ctx *ctx, chess_progress_fn fn, void *user, int32_t every) {
+    if (!ctx) return CHESS_E_ARG;
+    if (fn && every <= 0) {
+        ctx->err = "chess_set_progress: every must be positive";
+        return CHESS_E_ARG;
+    }
+    ctx->progress = fn;
+    ctx->progress_user = user;
+    ctx->progress_every = fn ? every : 0;
     return CHESS_OK;
 }
 

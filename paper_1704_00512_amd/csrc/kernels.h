@@ -76,6 +76,12 @@ struct ListedPlanDev {
     int max_bt_row = 0;
     int max_entries = 0;
     int entry_width = 1;
+    // kernel variant (MFMA paths only; others have variant 0 alone):
+    //   0: Bt rows staged in LDS, 8 waves (float) / 4 waves (double)
+    //   1: Bt operands read from global memory, same wave count
+    //   2: Bt operands from global memory, twice the waves
+    //   3: Bt operands from global memory, half the waves
+    int variant = 0;
     const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
     const int64_t *j_off = nullptr;      // [ntiles + 1]
     const int32_t *j_rec = nullptr;      // [total_j * 8]
@@ -85,6 +91,8 @@ struct ListedPlanDev {
 hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
                                  const ProductOperands &ops, const Epilogue &ep, hipStream_t st);
 size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan);
+// number of kernel variants for this dtype / b / plan.cmax (>= 1)
+int listed_product_variants(int dtype, int b, const ListedPlanDev &plan);
 
 // dtype: 0 = double, 1 = float.  Returns a hipError_t.
 hipError_t launch_masked_product(int dtype, int b, const ProductPlanDev &plan,

@@ -44,14 +44,14 @@ struct ListedLds {
     size_t a, wave, wave_bt, wave_ent, total;
 };
 
-template <typename T, int B, int NW, int EW>
+template <typename T, int B, int NW, int EW, bool BD>
 __host__ __device__ inline ListedLds listed_lds(const ListedPlanDev &p) {
     ListedLds L;
     L.a = 0;
     // A tile, then one block of zeros (the operand of padded MFMA slots)
     L.wave = al16((size_t)(p.lds_ablocks + 1) * B * B * sizeof(T));
     // Bt rows are staged only for b = 4 (16-byte chunks); b = 9 reads them from global memory
-    L.wave_bt = ((B * B * sizeof(T)) % 16 == 0)
+    L.wave_bt = (!BD && (B * B * sizeof(T)) % 16 == 0)
                     ? (((size_t)p.max_bt_row * B * B * sizeof(T) / 16 + 63) / 64) * 64 * 16
                     : 0;
     L.wave_ent = al16((size_t)kEntWords * 64 * 4);
@@ -97,7 +97,7 @@ __device__ inline void decode(const void *ent, int idx, int &pa, int &sl) {
     }
 }
 
-template <typename T, int B, int CMAX, int NW, int MODE, int EW>
+template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD>
 __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductOperands ops,
                                                     Epilogue ep) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -106,11 +106,14 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     constexpr bool MFMA = MODE == 1;
     constexpr bool MF64 = MODE == 2;
     constexpr int NE = (MFMA || MF64) ? 1 : (CMAX * BB + 63) / 64;
-    constexpr bool V16OK = (BB * sizeof(T)) % 16 == 0;
+    // BD: MFMA operands of Bt come straight from global memory (L1/L2) and
+    // Bt rows are not staged in LDS
+    constexpr bool V16OK = !BD && (BB * sizeof(T)) % 16 == 0;
     constexpr int V16 = V16OK ? (BB * (int)sizeof(T)) / 16 : 1;
     constexpr int RBV = V16OK ? (128 * V16 + 63) / 64 : 1;  // Bt rows up to 128 blocks
     static_assert(!MFMA || (B == 4 && CMAX == 4 && sizeof(T) == 4), "MFMA path: float, b = 4");
     static_assert(!MF64 || (B == 4 && CMAX == 4 && sizeof(T) == 8), "MFMA64 path: double, b = 4");
+    static_assert(!BD || MFMA || MF64, "direct Bt operands: MFMA paths only");
 
     const int ntiles = plan.ntiles;
     const int nt8 = (ntiles + 7) & ~7;
@@ -119,7 +122,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     // contiguous range of tiles so neighbouring tiles share its L2.
     const int tile = (w & 7) * (nt8 >> 3) + (w >> 3);
     if (tile >= ntiles) return;
-    const ListedLds L = listed_lds<T, B, NW, EW>(plan);
+    const ListedLds L = listed_lds<T, B, NW, EW, BD>(plan);
     const int row0 = plan.tile_row0[tile];
     const int c = plan.tile_row0[tile + 1] - row0;
     const int64_t ab0 = ops.a_rp[row0];
@@ -321,13 +324,18 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             nmax = __builtin_amdgcn_readfirstlane(nmax);
             typedef __attribute__((address_space(3))) const unsigned char lds_u8;
             typedef __attribute__((address_space(3))) const f32x4 lds_f4;
+            // Bt operands: LDS (staged row) or global memory (BD)
+            typedef typename std::conditional<BD, const unsigned char, lds_u8>::type b_u8;
+            typedef typename std::conditional<BD, const f32x4, lds_f4>::type b_f4;
             lds_u8 *zp = (lds_u8 *)(As + (size_t)plan.lds_ablocks * BB);
             lds_u8 *a_base = (lds_u8 *)(As + rs * BB) + q * 16;
-            lds_u8 *b_base = (lds_u8 *)bsrc + q * 16;
+            b_u8 *b_base = (b_u8 *)bsrc + q * 16;
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const int iters = (nmax + 3) >> 2;
             // operand addresses of hit h of this slot (zero block past the list)
-            auto addr = [&](int hh, lds_u8 *&ap, lds_u8 *&bp) {
+            // (past the end: A reads the zero block; B reads a block of the
+            // row, finite, so the product is exactly zero)
+            auto addr = [&](int hh, lds_u8 *&ap, b_u8 *&bp) {
                 uint32_t pa, sl;
                 if constexpr (EW == 1) {
                     const uint32_t e = reinterpret_cast<const uint16_t *>(entw)[omine + hh];
@@ -340,19 +348,23 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
                 }
                 const bool ok = hh < nmine;
                 ap = ok ? a_base + (pa << 6) : zp;
-                bp = ok ? b_base + (sl << 6) : zp;
+                if constexpr (BD)
+                    bp = b_base + ((ok ? sl : 0u) << 6);
+                else
+                    bp = ok ? b_base + (sl << 6) : zp;
             };
             int it = 0;
             // four hits per slot at a time: all LDS reads issued before the MFMAs
             for (; it + 4 <= iters; it += 4) {
-                lds_u8 *ap[4], *bp[4];
+                lds_u8 *ap[4];
+                b_u8 *bp[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) addr(grp + 4 * (it + u), ap[u], bp[u]);
                 f32x4 a[4], bb[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     a[u] = *(lds_f4 *)ap[u];
-                    bb[u] = *(lds_f4 *)bp[u];
+                    bb[u] = *(b_f4 *)bp[u];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -363,10 +375,11 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
                 }
             }
             for (; it < iters; ++it) {
-                lds_u8 *ap, *bp;
+                lds_u8 *ap;
+                b_u8 *bp;
                 addr(grp + 4 * it, ap, bp);
                 const f32x4 a = *(lds_f4 *)ap;
-                const f32x4 bb = *(lds_f4 *)bp;
+                const f32x4 bb = *(b_f4 *)bp;
                 acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[0], bb[0], acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[1], bb[1], acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[2], bb[2], acc, 0, 0, 0);
@@ -403,12 +416,14 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             nmax = __builtin_amdgcn_readfirstlane(nmax);
             typedef __attribute__((address_space(3))) const unsigned char lds_u8;
             typedef __attribute__((address_space(3))) const double lds_d;
+            typedef typename std::conditional<BD, const unsigned char, lds_u8>::type b_u8;
+            typedef typename std::conditional<BD, const double, lds_d>::type b_d;
             lds_u8 *zp = (lds_u8 *)(As + (size_t)plan.lds_ablocks * BB);
             const int eoffb = (x * 4 + t) * 8;
             lds_u8 *a_base = (lds_u8 *)(As + rs * BB) + eoffb;
-            lds_u8 *b_base = (lds_u8 *)bsrc + eoffb;
+            b_u8 *b_base = (b_u8 *)bsrc + eoffb;
             double acc = 0.0;
-            auto addr = [&](int hh, lds_u8 *&ap, lds_u8 *&bp) {
+            auto addr = [&](int hh, lds_u8 *&ap, b_u8 *&bp) {
                 uint32_t pa, sl;
                 if constexpr (EW == 1) {
                     const uint32_t e = reinterpret_cast<const uint16_t *>(entw)[omine + hh];
@@ -421,26 +436,31 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
                 }
                 const bool ok = hh < nmine;
                 ap = ok ? a_base + (pa << 7) : zp;
-                bp = ok ? b_base + (sl << 7) : zp;
+                if constexpr (BD)
+                    bp = b_base + ((ok ? sl : 0u) << 7);
+                else
+                    bp = ok ? b_base + (sl << 7) : zp;
             };
             int h = 0;
             for (; h + 4 <= nmax; h += 4) {
-                lds_u8 *ap[4], *bp[4];
+                lds_u8 *ap[4];
+                b_u8 *bp[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) addr(h + u, ap[u], bp[u]);
                 double a[4], bb[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     a[u] = *(lds_d *)ap[u];
-                    bb[u] = *(lds_d *)bp[u];
+                    bb[u] = *(b_d *)bp[u];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u], bb[u], acc, 0, 0, 0);
             }
             for (; h < nmax; ++h) {
-                lds_u8 *ap, *bp;
+                lds_u8 *ap;
+                b_u8 *bp;
                 addr(h, ap, bp);
-                acc = __builtin_amdgcn_mfma_f64_4x4x4f64(*(lds_d *)ap, *(lds_d *)bp, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f64_4x4x4f64(*(lds_d *)ap, *(b_d *)bp, acc, 0, 0, 0);
             }
             y[0] = (T)acc;
         } else {
@@ -518,20 +538,19 @@ struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
     static constexpr int MODE = (B == 4 && CMAX == 4) ? (std::is_same<T, float>::value ? 1 : 2) : 0;
     static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
+    static constexpr int COUNT = MODE == 0 ? 1 : 4;
 };
 
-template <typename T, int B, int CMAX, int EW>
-hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD>
+hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
                     hipStream_t st, size_t *lds_out) {
-    constexpr int NW = LVariant<T, B, CMAX>::NW;
-    constexpr int MODE = LVariant<T, B, CMAX>::MODE;
-    const size_t lds = listed_lds<T, B, NW, EW>(plan).total;
+    const size_t lds = listed_lds<T, B, NW, EW, BD>(plan).total;
     if (lds_out) {
         *lds_out = lds;
         return hipSuccess;
     }
     if (plan.ntiles == 0) return hipSuccess;
-    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW>;
+    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW, BD>;
     static int raised_device = -1;
     static size_t raised_to = 0;
     int dev = 0;
@@ -543,9 +562,29 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
         raised_to = lds;
     }
     const int nt8 = (plan.ntiles + 7) & ~7;
-    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW>), dim3(nt8), dim3(64 * NW), lds, st,
+    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW, BD>), dim3(nt8), dim3(64 * NW), lds, st,
                        plan, ops, ep);
     return hipGetLastError();
+}
+
+template <typename T, int B, int CMAX, int EW>
+hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                    hipStream_t st, size_t *lds_out) {
+    typedef LVariant<T, B, CMAX> V;
+    constexpr int NW = V::NW;
+    constexpr int MODE = V::MODE;
+    if constexpr (MODE == 0) {
+        if (plan.variant != 0) return hipErrorInvalidValue;
+        return launch_v<T, B, CMAX, NW, MODE, EW, false>(plan, ops, ep, st, lds_out);
+    } else {
+        switch (plan.variant) {
+            case 0: return launch_v<T, B, CMAX, NW, MODE, EW, false>(plan, ops, ep, st, lds_out);
+            case 1: return launch_v<T, B, CMAX, NW, MODE, EW, true>(plan, ops, ep, st, lds_out);
+            case 2: return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true>(plan, ops, ep, st, lds_out);
+            case 3: return launch_v<T, B, CMAX, NW / 2, MODE, EW, true>(plan, ops, ep, st, lds_out);
+            default: return hipErrorInvalidValue;
+        }
+    }
 }
 
 template <typename T, int B, int CMAX>
@@ -581,6 +620,11 @@ hipError_t dispatch_listed(int dtype, int b, const ListedPlanDev &plan, const Pr
 hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
                                  const ProductOperands &ops, const Epilogue &ep, hipStream_t st) {
     return dispatch_listed(dtype, b, plan, ops, ep, st, nullptr);
+}
+
+int listed_product_variants(int dtype, int b, const ListedPlanDev &plan) {
+    if (b != 4 || plan.cmax != 4) return 1;
+    return dtype == 0 ? LVariant<double, 4, 4>::COUNT : LVariant<float, 4, 4>::COUNT;
 }
 
 size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan) {

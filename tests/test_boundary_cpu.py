@@ -30,7 +30,7 @@ def test_header_declares_the_api():
     names = declared_functions()
     for n in ("chess_fermi_operator", "chess_matrix_power", "chess_eigs_in_interval",
               "chess_create", "chess_destroy", "chess_last_error", "chess_default_opts",
-              "chess_chebyshev", "chess_masked_product"):
+              "chess_chebyshev", "chess_masked_product", "chess_set_progress"):
         assert n in names
 
 
@@ -80,6 +80,8 @@ def test_null_context_is_rejected(lib):
     assert lib.chess_destroy(None) == -1
     assert lib.chess_last_error(None) == b"null context"
     assert lib.chess_fermi_operator(None, None, None, None, 1.0, 0.1, None, None, None) == -1
+    from paper_1704_00512_amd import _lib
+    assert lib.chess_set_progress(None, _lib.PROGRESS_FN(), None, 0) == -1
 
 
 def test_product_path_imports_no_oracle():

@@ -101,6 +101,29 @@ def test_chebyshev_chain_parity(gpu_ctx, spec, precision, tol):
         assert np.max(np.abs(got - ref)) < tol, (precision, q)
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_chain_kernel_variants(gpu_ctx, monkeypatch, variant, precision, tol):
+    # every variant of the b = 4 chain kernel, forced, against the oracle
+    monkeypatch.setenv("CHESS_LISTED_VARIANT", str(variant))
+    s, accs, mom, acc_o, mom_o = chain_case(gpu_ctx, SYS4, 70, precision)
+    assert np.max(np.abs(mom - mom_o)) < tol * s.n
+    for q in range(2):
+        ref = bm(s.pat_k).to_block(acc_o[q])
+        assert np.max(np.abs(accs[q].cpu().numpy() - ref)) < tol, (variant, precision, q)
+    s2 = system(*SYS4, kT=0.02)
+    _, info = chess_fermi_operator(gpu_ctx, dt(s2.H), gpat(s2.pat_h), dt(s2.S), gpat(s2.pat_h),
+                                   gpat(s2.pat_k), s2.n_electrons, s2.kT, precision=precision,
+                                   mu=-0.95, **FIX)
+    assert info["kernel_variant"] == variant
+
+
+def test_chain_kernel_variant_out_of_range(gpu_ctx, monkeypatch):
+    monkeypatch.setenv("CHESS_LISTED_VARIANT", "7")
+    with pytest.raises(ChessError):
+        chain_case(gpu_ctx, SYS4, 10, "f32")
+
+
 @pytest.mark.parametrize("n_pl", [1, 2, 3])
 def test_chebyshev_chain_shortest(gpu_ctx, n_pl):
     s, accs, mom, acc_o, mom_o = chain_case(gpu_ctx, SYS4, n_pl, "f64", nq=1)
