@@ -119,6 +119,72 @@ def cpu_baseline(sysm, budget_s=20.0):
                 ms_per_step=round(dt / nprod * 1e3, 2))
 
 
+def bench_batched(args):
+    """The batched form: 48 systems (K at 3 trial mu, S^-1/2, S^-1 from one
+    chain per matrix) in one call, against one single-system call per system
+    (K at one mu, S^-1/2 inside)."""
+    import multiprocessing as mp
+    import torch
+    from paper_1704_00512_amd import (BlockPattern, Context, chess_fermi_operator,
+                                      chess_fermi_operator_batched)
+    from workloads.generator import BATCH_SYSTEMS, batched_system
+    t0 = time.time()
+    with mp.get_context("spawn").Pool(12) as pool:
+        ss = []
+        for k, s in enumerate(pool.imap(batched_system, range(BATCH_SYSTEMS))):
+            ss.append(s)
+            if (k + 1) % 8 == 0:
+                log(f"generated {k + 1}/{BATCH_SYSTEMS} systems ({time.time() - t0:.0f} s)")
+    dev = torch.device("cuda:0")
+    mu_tr = (-0.55, -0.5, -0.45)
+    args_b = []
+    for s in ss:
+        ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx, dev)
+        pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx, dev)
+        args_b.append(dict(H=torch.tensor(s.H, device=dev), pat_h=ph, S=torch.tensor(s.S, device=dev),
+                           pat_s=ph, pattern=pk, n_electrons=s.n_electrons, kT=s.kT, mu_trial=mu_tr))
+    rows = sum(s.n for s in ss)
+    log(f"{len(ss)} systems, {rows} rows, b=4: {sum(s.b == 4 for s in ss)}, b=9: {sum(s.b == 9 for s in ss)}")
+    ctx = Context(0)
+    opts = dict(precision="f32", bounds_mode="lanczos", tol_fit=1e-6, tol_fit_s=1e-7)
+    times = []
+    for i in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = chess_fermi_operator_batched(ctx, args_b, **opts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) * 1e3
+        log(f"batched call {i}: {dt:.0f} ms (chain kernels {res[0]['info']['ms_chain_kernel']:.0f} ms)")
+        if i >= args.warmup:
+            times.append(dt)
+    ms_b = sum(times) / len(times)
+    npl = [r["info"]["n_pl"] for r in res]
+    # one single-system call per system (its plans warmed first)
+    for a in args_b:
+        chess_fermi_operator(ctx, a["H"], a["pat_h"], a["S"], a["pat_s"], a["pattern"],
+                             a["n_electrons"], a["kT"], mu=mu_tr[1], **opts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k, a in enumerate(args_b):
+        chess_fermi_operator(ctx, a["H"], a["pat_h"], a["S"], a["pat_s"], a["pattern"],
+                             a["n_electrons"], a["kT"], mu=mu_tr[1], **opts)
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t) * 1e3
+    log(f"sequential single-system calls: {ms_seq:.0f} ms")
+    ctx.close()
+    out = dict(metric="batched Fermi-operator time to solution (K at 3 trial mu, S^-1/2, S^-1 "
+                      "per system, one call)",
+               value=round(ms_b, 1), unit="ms", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=round(ms_b, 1), higher_is_better=False, scaling="weak", vs_baseline=None,
+               dtype="f32", data="synthetic",
+               config=dict(workload=f"batched48: {len(ss)} systems, 200-4000 atoms, b 4|9, "
+                                    f"{rows} rows in total, kT 0.005, half filling",
+                           n_pl_min=min(npl), n_pl_max=max(npl)),
+               sequential_single_system_ms=round(ms_seq, 1),
+               speedup_vs_sequential=round(ms_seq / ms_b, 2))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +203,10 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.workload == "batched48":
+        bench_batched(args)
+        return
 
     if args.calibrate_copy:
         n = 1 << 28  # 2^28 float32 = 1 GiB read + 1 GiB written per copy

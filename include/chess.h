@@ -73,7 +73,10 @@ enum {
  * eigenvalue bounds and polynomial degree"). */
 enum {
     CHESS_BOUNDS_GERSHGORIN = 0, /* Gershgorin discs: rigorous, wide */
-    CHESS_BOUNDS_LANCZOS = 1     /* a few Lanczos steps plus a margin: tight, checked by Eq. 6 */
+    CHESS_BOUNDS_LANCZOS = 1,    /* a few Lanczos steps plus a margin: tight, checked by Eq. 6 */
+    CHESS_BOUNDS_LEARNED = 2     /* the loaded predictor (chess_model_load): bounds and a mu
+                                    bracket from matrix statistics, checked by Eq. 6 and the
+                                    growth test; the Gershgorin interval is the fallback */
 };
 
 typedef struct chess_ctx chess_ctx;
@@ -130,7 +133,128 @@ typedef struct {
     int32_t kernel_variant; /* variant of the chain product kernel chosen by timing, or
                                forced by CHESS_LISTED_VARIANT in the environment
                                (-1: the searching kernel) */
+    int32_t fallback;       /* CHESS_BOUNDS_LEARNED: bit 0 = predicted bounds rejected (Eq. 6
+                               or growth test) and replaced by the Gershgorin interval,
+                               bit 1 = mu not inside the predicted bracket */
+    double pred_lo, pred_hi, pred_mu; /* predictor outputs (NaN unless CHESS_BOUNDS_LEARNED) */
+    double ms_learned;      /* features + inference time */
 } chess_info;
+
+/*
+ * A batch of independent systems (each as in chess_fermi_operator) that
+ * share the work of one call: per block edge b, the systems are laid out
+ * block-diagonally and every chain runs once over the whole batch - one S
+ * chain giving S^-1/2 and S^-1 (Sec. "Matrix powers": both powers from the
+ * same T_k), one chain on H~' accumulating K' at three trial chemical
+ * potentials (Eq. 1 with three coefficient sets on the same T_k), with the
+ * moments Tr T_k of every system, and the sandwich products of Sec. "Fermi
+ * Operator Expansion" run once over the batch.  Row tiles never straddle
+ * systems, so each system keeps its own bounds, degree n_pl (terms past it
+ * have zero weight), coefficients and moments.  The products of each chain
+ * after the first are recorded into one HIP graph and launched as one graph
+ * (CHESS_BATCH_GRAPH=0 in the environment launches them one by one).  The
+ * kernel variant is chosen by timing as for single systems.
+ * Per system (all matrices device, float64):
+ *   H, S, pattern, n_electrons, kT : as for chess_fermi_operator
+ *   mu_trial[3] : chemical potentials at which K is formed; NaN entries take
+ *                 mu^ - d, mu^, mu^ + d from the loaded predictor
+ *                 (opts->bounds_mode = CHESS_BOUNDS_LEARNED, d = its bracket
+ *                 half width), otherwise CHESS_E_ARG
+ *   K_out[3]    : K at mu_trial[q] on exactly `pattern`, or NULL (not formed)
+ *   Sinvhalf_out, Sinv_out : S^-1/2 and S^-1 on `pattern`, or NULL
+ *   ne_trial    : host, 3 doubles or NULL: N(mu_trial[q]) from the moments
+ *   info        : host or NULL: mu = the root of N(mu) = N_e from the moments,
+ *                 lo, hi, s_lo, s_hi, n_pl, n_pl_s, penalty, tr_ks (of K at
+ *                 mu_trial[1]), ne_chain = N(mu_trial[1]); ms_total and
+ *                 ms_chain_kernel are those of the whole call
+ * The batch form does not widen bounds: a system failing Eq. 6 or the growth
+ * test returns CHESS_E_BOUNDS.  opts apply to every system.
+ */
+typedef struct {
+    const chess_matrix *H;
+    const chess_matrix *S;
+    const chess_pattern *pattern;
+    double n_electrons;
+    double kT;
+    double mu_trial[3];
+    chess_matrix *K_out[3];
+    chess_matrix *Sinvhalf_out;
+    chess_matrix *Sinv_out;
+    double *ne_trial;
+    chess_info *info;
+} chess_batch_item;
+
+int chess_fermi_operator_batched(chess_ctx *ctx, int32_t nsys, const chess_batch_item *items,
+                                 const chess_opts *opts);
+
+/*
+ * Learned predictor of the spectral bounds and of mu.
+ *
+ * The paper notes that good initial bounds avoid recomputing the expansion
+ * after a failed Eq. 6 check (Sec. "Determination of the eigenvalue bounds and
+ * polynomial degree") and save the bound search (Sec. "Scaling with spectral
+ * properties").  A two-layer perceptron maps CHESS_N_FEATURES statistics of H'
+ * (Gershgorin interval, diagonal and radius histograms, Tr T_k for k <= 8,
+ * kT, filling, size) to (eps_min, eps_max, mu) in units of the Gershgorin
+ * interval: y = c + w * (W2 tanh(W1 x~ + b1) + b2) * y_std + y_mean, with
+ * x~ = (x - x_mean) * x_inv_std, c and w the centre and half width.
+ *
+ * Parameter vector (float32, CHESS_MLP_PARAMS): W1 [128][64], b1 [128],
+ * W2 [3][128], b2 [3], row-major.  Normalisation block (CHESS_MLP_NORM):
+ * x_mean [64], x_inv_std [64], y_mean [3], y_std [3].
+ * Model blob (CHESS_MODEL_FLOATS): normalisation block, then
+ * {margin_lo, margin_hi, mu_half} in Gershgorin half widths, then the
+ * parameters.  Bounds used: [eps_min - margin_lo w, eps_max + margin_hi w]
+ * clipped to the Gershgorin interval; mu bracket: mu -+ mu_half w.
+ */
+#define CHESS_N_FEATURES 64
+#define CHESS_MLP_HIDDEN 128
+#define CHESS_MLP_OUT 3
+#define CHESS_MLP_PARAMS (128 * 64 + 128 + 3 * 128 + 3)
+#define CHESS_MLP_NORM (2 * 64 + 2 * 3)
+#define CHESS_MODEL_FLOATS (CHESS_MLP_NORM + 3 + CHESS_MLP_PARAMS)
+
+/*
+ * Features of (H, S) on `pattern` (as for chess_fermi_operator): builds the
+ * orthogonal frame (S^-1/2 chain, H'), then the statistics listed above.
+ *   feat_out  : host, CHESS_N_FEATURES floats
+ *   gersh_out : host, 2 doubles (Gershgorin interval of H'), may be NULL
+ * Synchronises before returning.
+ */
+int chess_features(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
+                   const chess_pattern *pattern, double n_electrons, double kT, float *feat_out,
+                   double *gersh_out, const chess_opts *opts);
+
+/*
+ * Perceptron forward pass on `batch` rows (all pointers device, float32):
+ *   x [batch][64] -> y [batch][3]; hidden [batch][128] receives the tanh
+ *   outputs if not NULL; norm (CHESS_MLP_NORM floats) applies the
+ *   normalisation block, NULL = identity.  Stream-ordered (no wait).
+ */
+int chess_mlp_forward(chess_ctx *ctx, const float *params, const float *norm, const float *x,
+                      int32_t batch, float *hidden, float *y);
+/*
+ * Gradient of L = 1/(2 batch) sum (y - target)^2 with respect to the
+ * parameters, from a forward pass without normalisation (x, hidden, y as it
+ * wrote them).  work: device, batch * (3 + 128) floats of scratch owned by
+ * the caller; grad: device, CHESS_MLP_PARAMS floats (overwritten); loss: host,
+ * may be NULL (when given, the call waits for it).  Sums over the batch run
+ * in a fixed order in float64.
+ */
+int chess_mlp_grad(chess_ctx *ctx, const float *params, const float *x, const float *hidden,
+                   const float *y, const float *target, int32_t batch, float *work, float *grad,
+                   double *loss);
+/*
+ * Adam step `step` (1, 2, ...) on n parameters (device): m, v are the moment
+ * estimates (zero before step 1), bias-corrected.  Stream-ordered.
+ */
+int chess_mlp_adam(chess_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n,
+                   float lr, float beta1, float beta2, float eps, int32_t step);
+/* Loads a model blob (host, n = CHESS_MODEL_FLOATS) into the context for
+ * CHESS_BOUNDS_LEARNED; CHESS_E_ARG for a wrong size, non-finite entries or a
+ * non-positive inverse scale.  chess_model_save copies the loaded blob back. */
+int chess_model_load(chess_ctx *ctx, const float *blob, int64_t n);
+int chess_model_save(const chess_ctx *ctx, float *blob, int64_t n);
 
 /* Fills *opts with the defaults listed above. */
 void chess_default_opts(chess_opts *opts);

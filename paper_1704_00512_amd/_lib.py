@@ -56,15 +56,35 @@ class chess_info(ctypes.Structure):
                 ("ms_s_chain", ctypes.c_double), ("ms_transform", ctypes.c_double),
                 ("ms_h_chain", ctypes.c_double), ("ms_mu", ctypes.c_double),
                 ("ms_post", ctypes.c_double), ("ms_chain_kernel", ctypes.c_double),
-                ("kernel_variant", ctypes.c_int32)]
+                ("kernel_variant", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("pred_lo", ctypes.c_double), ("pred_hi", ctypes.c_double),
+                ("pred_mu", ctypes.c_double), ("ms_learned", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class chess_batch_item(ctypes.Structure):
+    _fields_ = [("H", ctypes.POINTER(chess_matrix)), ("S", ctypes.POINTER(chess_matrix)),
+                ("pattern", ctypes.POINTER(chess_pattern)), ("n_electrons", ctypes.c_double),
+                ("kT", ctypes.c_double), ("mu_trial", ctypes.c_double * 3),
+                ("K_out", ctypes.POINTER(chess_matrix) * 3),
+                ("Sinvhalf_out", ctypes.POINTER(chess_matrix)),
+                ("Sinv_out", ctypes.POINTER(chess_matrix)),
+                ("ne_trial", ctypes.POINTER(ctypes.c_double)),
+                ("info", ctypes.POINTER(chess_info))]
+
+
 EXPORTS = ["chess_default_opts", "chess_create", "chess_destroy", "chess_last_error",
            "chess_fermi_operator", "chess_matrix_power", "chess_eigs_in_interval",
-           "chess_chebyshev", "chess_masked_product", "chess_set_progress"]
+           "chess_chebyshev", "chess_masked_product", "chess_set_progress",
+           "chess_features", "chess_mlp_forward", "chess_mlp_grad", "chess_mlp_adam",
+           "chess_model_load", "chess_model_save", "chess_fermi_operator_batched"]
+
+N_FEATURES, MLP_HIDDEN, MLP_OUT = 64, 128, 3
+MLP_PARAMS = MLP_HIDDEN * N_FEATURES + MLP_HIDDEN + MLP_OUT * MLP_HIDDEN + MLP_OUT
+MLP_NORM = 2 * N_FEATURES + 2 * MLP_OUT
+MODEL_FLOATS = MLP_NORM + 3 + MLP_PARAMS
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64,
                                ctypes.c_int64)
@@ -103,6 +123,19 @@ def load():
                                   P(chess_opts)]
     L.chess_masked_product.argtypes = [vp, P(chess_matrix), P(chess_matrix), P(chess_matrix)]
     L.chess_set_progress.argtypes = [vp, PROGRESS_FN, vp, ctypes.c_int32]
+    fp = P(ctypes.c_float)
+    L.chess_features.argtypes = [vp, P(chess_matrix), P(chess_matrix), P(chess_pattern),
+                                 ctypes.c_double, ctypes.c_double, fp, P(ctypes.c_double),
+                                 P(chess_opts)]
+    L.chess_mlp_forward.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp]
+    L.chess_mlp_grad.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp, vp,
+                                 P(ctypes.c_double)]
+    L.chess_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32]
+    L.chess_fermi_operator_batched.argtypes = [vp, ctypes.c_int32, P(chess_batch_item),
+                                               P(chess_opts)]
+    L.chess_model_load.argtypes = [vp, fp, ctypes.c_int64]
+    L.chess_model_save.argtypes = [vp, fp, ctypes.c_int64]
     for name in EXPORTS:
         if name not in ("chess_default_opts", "chess_last_error"):
             getattr(L, name).restype = ctypes.c_int

@@ -78,7 +78,7 @@ def default_opts(**kw) -> _lib.chess_opts:
         elif k == "smearing" and isinstance(v, str):
             o.smearing = {"erfc": _lib.CHESS_ERFC, "fermi_dirac": _lib.CHESS_FERMI_DIRAC}[v]
         elif k == "bounds_mode" and isinstance(v, str):
-            o.bounds_mode = {"gershgorin": 0, "lanczos": 1}[v]
+            o.bounds_mode = {"gershgorin": 0, "lanczos": 1, "learned": 2}[v]
         else:
             setattr(o, k, v)
     return o
@@ -197,3 +197,134 @@ def chess_masked_product(ctx: Context, A: torch.Tensor, pat_a: BlockPattern, B: 
     ctx._check(ctx._L.chess_masked_product(ctx._h, ctypes.byref(ma), ctypes.byref(mb),
                                            ctypes.byref(mc)))
     return C
+
+
+# ---------------------------------------------------------------------------
+# learned predictor of bounds and mu
+# ---------------------------------------------------------------------------
+
+def chess_features(ctx: Context, H: torch.Tensor, pat_h: BlockPattern, S: torch.Tensor,
+                   pat_s: BlockPattern, pattern: BlockPattern, n_electrons: float, kT: float,
+                   **opts):
+    """(features [64] float32 numpy, Gershgorin interval of H' (lo, hi))."""
+    f = np.zeros(_lib.N_FEATURES, dtype=np.float32)
+    g = np.zeros(2)
+    mh, ms, pk = _mat(pat_h, H), _mat(pat_s, S), pattern.c()
+    o = default_opts(**opts)
+    ctx._check(ctx._L.chess_features(
+        ctx._h, ctypes.byref(mh), ctypes.byref(ms), ctypes.byref(pk), float(n_electrons),
+        float(kT), f.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+        g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(o)))
+    return f, (float(g[0]), float(g[1]))
+
+
+def _fptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def chess_mlp_forward(ctx: Context, params: torch.Tensor, x: torch.Tensor,
+                      norm: torch.Tensor | None = None, want_hidden: bool = False):
+    """y [B, 3] (and the hidden activations [B, 128] if want_hidden)."""
+    B = x.shape[0]
+    y = torch.empty((B, _lib.MLP_OUT), dtype=torch.float32, device=x.device)
+    hid = torch.empty((B, _lib.MLP_HIDDEN), dtype=torch.float32, device=x.device) if want_hidden else None
+    ctx._check(ctx._L.chess_mlp_forward(ctx._h, _fptr(params), _fptr(norm), _fptr(x), int(B),
+                                        _fptr(hid), _fptr(y)))
+    return (y, hid) if want_hidden else y
+
+
+def chess_mlp_grad(ctx: Context, params, x, hidden, y, target, work=None, grad=None,
+                   want_loss: bool = True):
+    """(grad [CHESS_MLP_PARAMS], loss or None)."""
+    B = x.shape[0]
+    if work is None:
+        work = torch.empty(B * (_lib.MLP_OUT + _lib.MLP_HIDDEN), dtype=torch.float32, device=x.device)
+    if grad is None:
+        grad = torch.empty(_lib.MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = ctypes.c_double(float("nan"))
+    ctx._check(ctx._L.chess_mlp_grad(ctx._h, _fptr(params), _fptr(x), _fptr(hidden), _fptr(y),
+                                     _fptr(target), int(B), _fptr(work), _fptr(grad),
+                                     ctypes.byref(loss) if want_loss else None))
+    return grad, (loss.value if want_loss else None)
+
+
+def chess_mlp_adam(ctx: Context, params, grad, m, v, step: int, lr: float, beta1=0.9,
+                   beta2=0.999, eps=1e-8):
+    ctx._check(ctx._L.chess_mlp_adam(ctx._h, _fptr(params), _fptr(grad), _fptr(m), _fptr(v),
+                                     int(params.numel()), float(lr), float(beta1), float(beta2),
+                                     float(eps), int(step)))
+
+
+def chess_model_load(ctx: Context, blob: np.ndarray):
+    b = np.ascontiguousarray(blob, dtype=np.float32)
+    ctx._check(ctx._L.chess_model_load(ctx._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                       int(b.size)))
+
+
+def chess_model_save(ctx: Context) -> np.ndarray:
+    b = np.zeros(_lib.MODEL_FLOATS, dtype=np.float32)
+    rc = ctx._L.chess_model_save(ctx._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(b.size))
+    if rc != 0:
+        raise ChessError(rc, "no model loaded")
+    return b
+
+
+# ---------------------------------------------------------------------------
+# batches of independent systems
+# ---------------------------------------------------------------------------
+
+def chess_fermi_operator_batched(ctx: Context, systems, want_k=(True, True, True),
+                                 want_sinvhalf: bool = True, want_sinv: bool = True, **opts):
+    """systems: list of dicts with H, pat_h, S, pat_s, pattern, n_electrons,
+    kT and optionally mu_trial (3 values; NaN / missing: predicted).
+    Returns one dict per system: K (list of 3 tensors or None), Sinvhalf,
+    Sinv, ne_trial (3 floats), info."""
+    n = len(systems)
+    items = (_lib.chess_batch_item * n)()
+    keep = []  # ctypes objects that must outlive the call
+    outs = []
+    for i, sy in enumerate(systems):
+        pk = sy["pattern"]
+        mh, ms, pc = _mat(sy["pat_h"], sy["H"]), _mat(sy["pat_s"], sy["S"]), pk.c()
+        it = items[i]
+        it.H, it.S, it.pattern = ctypes.pointer(mh), ctypes.pointer(ms), ctypes.pointer(pc)
+        it.n_electrons, it.kT = float(sy["n_electrons"]), float(sy["kT"])
+        mt = sy.get("mu_trial", (float("nan"),) * 3)
+        for q in range(3):
+            it.mu_trial[q] = float(mt[q])
+        res = dict(K=[None] * 3, Sinvhalf=None, Sinv=None)
+        mats = []
+        for q in range(3):
+            if want_k[q]:
+                res["K"][q] = pk.zeros()
+                m = _mat(pk, res["K"][q])
+                it.K_out[q] = ctypes.pointer(m)
+                mats.append(m)
+        if want_sinvhalf:
+            res["Sinvhalf"] = pk.zeros()
+            m = _mat(pk, res["Sinvhalf"])
+            it.Sinvhalf_out = ctypes.pointer(m)
+            mats.append(m)
+        if want_sinv:
+            res["Sinv"] = pk.zeros()
+            m = _mat(pk, res["Sinv"])
+            it.Sinv_out = ctypes.pointer(m)
+            mats.append(m)
+        ne = (ctypes.c_double * 3)()
+        info = _lib.chess_info()
+        it.ne_trial = ctypes.cast(ne, ctypes.POINTER(ctypes.c_double))
+        it.info = ctypes.pointer(info)
+        keep += [mh, ms, pc, ne, info] + mats
+        outs.append((res, ne, info))
+    o = default_opts(**opts)
+    ctx._check(ctx._L.chess_fermi_operator_batched(ctx._h, n, items, ctypes.byref(o)))
+    result = []
+    for res, ne, info in outs:
+        res["ne_trial"] = [ne[0], ne[1], ne[2]]
+        res["info"] = info.as_dict()
+        result.append(res)
+    return result

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -140,8 +141,19 @@ struct ListedPlan {
     int dtype = 0;
     bool usable = false;  // false: rows too long for the list format
     int tuned_variant = -1;  // fastest kernel variant on this plan (-1: not timed yet)
+    std::vector<int32_t> breaks;     // rows where a tile must start (batches: system starts)
+    std::vector<int32_t> tile_row0;  // host copy, ntiles + 1
     ListedPlanDev dev;
     DevBuf d_tile_row0, d_j_off, d_j_rec, d_entries;
+};
+
+// Learned bound / mu predictor loaded by chess_model_load (layout of the
+// blob: see CHESS_MODEL_FLOATS in chess.h).
+struct Model {
+    bool loaded = false;
+    std::vector<float> blob;
+    DevBuf norm, params;
+    double margin_lo = 0, margin_hi = 0, mu_half = 0;  // in Gershgorin half widths
 };
 
 }  // namespace chess
@@ -157,6 +169,9 @@ struct chess_ctx {
     chess_progress_fn progress = nullptr;
     void *progress_user = nullptr;
     int32_t progress_every = 0;
+    chess::Model model;
+    chess::DevBuf loss_buf;  // one float64: loss of chess_mlp_grad
+    hipStream_t capture_stream = nullptr;  // records graphs (not the null stream)
 };
 
 namespace chess {
@@ -170,30 +185,26 @@ static void validate_pattern_struct(const chess_pattern *p, const char *what) {
 
 // Copies a caller pattern to the host, validates it and returns the cached
 // entry with identical content (or a new one).
-static const Pattern *get_pattern(chess_ctx *ctx, const chess_pattern *p, const char *what) {
-    validate_pattern_struct(p, what);
+static const Pattern *get_pattern_host(chess_ctx *ctx, int b, int nbrows, int64_t nnzb,
+                                       std::vector<int64_t> rp, std::vector<int32_t> ci,
+                                       const char *what) {
     hipStream_t st = ctx->stream;
-    std::vector<int64_t> rp((size_t)p->nbrows + 1);
-    std::vector<int32_t> ci((size_t)p->nnzb);
-    HIPCHECK(hipMemcpyAsync(rp.data(), p->row_ptr, rp.size() * 8, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipMemcpyAsync(ci.data(), p->col_idx, ci.size() * 4, hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
     for (auto &e : ctx->patterns) {
-        if (e->b == p->b && e->nb == p->nbrows && e->nnzb == p->nnzb && e->rp == rp && e->ci == ci)
+        if (e->b == b && e->nb == nbrows && e->nnzb == nnzb && e->rp == rp && e->ci == ci)
             return e.get();
     }
     auto P = std::make_unique<Pattern>();
-    P->b = p->b;
-    P->nb = p->nbrows;
-    P->nnzb = p->nnzb;
-    if (rp[0] != 0 || rp[p->nbrows] != p->nnzb) CHESS_THROW(CHESS_E_PATTERN, "%s: row_ptr must start at 0 and end at nnzb", what);
-    P->diag.assign(p->nbrows, -1);
-    for (int i = 0; i < p->nbrows; ++i) {
+    P->b = b;
+    P->nb = nbrows;
+    P->nnzb = nnzb;
+    if (rp[0] != 0 || rp[nbrows] != nnzb) CHESS_THROW(CHESS_E_PATTERN, "%s: row_ptr must start at 0 and end at nnzb", what);
+    P->diag.assign(nbrows, -1);
+    for (int i = 0; i < nbrows; ++i) {
         if (rp[i + 1] < rp[i]) CHESS_THROW(CHESS_E_PATTERN, "%s: row_ptr decreases at row %d", what, i);
         P->max_row = std::max<int>(P->max_row, (int)(rp[i + 1] - rp[i]));
         for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
             const int j = ci[q];
-            if (j < 0 || j >= p->nbrows) CHESS_THROW(CHESS_E_PATTERN, "%s: column %d out of range in row %d", what, j, i);
+            if (j < 0 || j >= nbrows) CHESS_THROW(CHESS_E_PATTERN, "%s: column %d out of range in row %d", what, j, i);
             if (q > rp[i] && ci[q - 1] >= j) CHESS_THROW(CHESS_E_PATTERN, "%s: columns not strictly increasing in row %d", what, i);
             if (j == i) P->diag[i] = q;
         }
@@ -201,9 +212,9 @@ static const Pattern *get_pattern(chess_ctx *ctx, const chess_pattern *p, const 
     }
     P->rp = std::move(rp);
     P->ci = std::move(ci);
-    P->tmap.assign((size_t)p->nnzb, -1);
-    std::vector<int32_t> brow((size_t)p->nnzb);
-    for (int i = 0; i < p->nbrows; ++i) {
+    P->tmap.assign((size_t)nnzb, -1);
+    std::vector<int32_t> brow((size_t)nnzb);
+    for (int i = 0; i < nbrows; ++i) {
         for (int64_t q = P->rp[i]; q < P->rp[i + 1]; ++q) {
             brow[q] = i;
             const int64_t t = P->find(P->ci[q], i);
@@ -219,6 +230,17 @@ static const Pattern *get_pattern(chess_ctx *ctx, const chess_pattern *p, const 
     HIPCHECK(hipStreamSynchronize(st));
     ctx->patterns.push_back(std::move(P));
     return ctx->patterns.back().get();
+}
+
+static const Pattern *get_pattern(chess_ctx *ctx, const chess_pattern *p, const char *what) {
+    validate_pattern_struct(p, what);
+    hipStream_t st = ctx->stream;
+    std::vector<int64_t> rp((size_t)p->nbrows + 1);
+    std::vector<int32_t> ci((size_t)p->nnzb);
+    HIPCHECK(hipMemcpyAsync(rp.data(), p->row_ptr, rp.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(ci.data(), p->col_idx, ci.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    return get_pattern_host(ctx, p->b, p->nbrows, p->nnzb, std::move(rp), std::move(ci), what);
 }
 
 static const EmbedMap *get_embed(chess_ctx *ctx, const Pattern *from, const Pattern *to,
@@ -374,14 +396,19 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
 // parallel over tiles.  Returns a plan with usable = false when a row is too
 // long for the list format; callers then use the searching kernel.
 static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Pattern *Bt,
-                                   const Pattern *C, int dtype) {
+                                   const Pattern *C, int dtype,
+                                   const std::vector<int32_t> &breaks = {}) {
     for (auto &e : ctx->lplans)
-        if (e->a == A && e->bt == Bt && e->c == C && e->dtype == dtype) return e.get();
+        if (e->a == A && e->bt == Bt && e->c == C && e->dtype == dtype && e->breaks == breaks) return e.get();
     auto P = std::make_unique<ListedPlan>();
     P->a = A;
     P->bt = Bt;
     P->c = C;
     P->dtype = dtype;
+    P->breaks = breaks;
+    std::vector<char> is_break((size_t)A->nb + 1, 0);
+    for (int32_t r : breaks)
+        if (r >= 0 && r <= A->nb) is_break[r] = 1;
     const int b = A->b;
     const int cmax = pick_cmax(dtype, b);
     const int ew = (A->max_row <= 255 && Bt->max_row <= 255) ? 1 : 2;
@@ -405,7 +432,7 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
         int64_t blocks = 0;
         while (r < A->nb && r - row0 < cmax) {
             const int64_t len = A->rp[r + 1] - A->rp[r];
-            if (r > row0 && blocks + len > budget_blocks) break;
+            if (r > row0 && (blocks + len > budget_blocks || is_break[r])) break;
             blocks += len;
             ++r;
         }
@@ -414,6 +441,7 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
     }
     const int ntiles = (int)tile_row0.size();
     tile_row0.push_back(A->nb);
+    P->tile_row0 = tile_row0;
     struct TileOut {
         std::vector<int32_t> rec;      // 8 per column; entry offsets relative to the tile
         std::vector<uint16_t> ent;     // entry_width 1
@@ -837,6 +865,145 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     HIPCHECK(hipStreamSynchronize(st));
 }
 
+// Chain over a batch of independent systems laid out block-diagonally: system
+// s owns block rows [row0[s], row0[s+1]) of PM and PK.  Row tiles never
+// straddle systems, so each tile's accumulator weight is that of its system
+// (coef_tab [nq][n_pl][nsys], zero past a system's own degree) and the trace
+// partials of a system's tiles sum to its moments (out [n_pl][nsys]).  The
+// products of steps 2 .. n_pl-2 are recorded once into a HIP graph and
+// launched as one graph.
+struct BatchChain {
+    const Pattern *PM = nullptr, *PK = nullptr;
+    const double *Mt = nullptr;
+    int n_pl = 0, nq = 0, dtype = 0;
+    const double *coef_tab = nullptr;
+    double *acc[4] = {nullptr, nullptr, nullptr, nullptr};
+    const std::vector<int32_t> *row0 = nullptr;
+    const int32_t *d_row_sys = nullptr;
+    bool use_graph = true;
+    std::vector<double> *moments = nullptr;
+    double kernel_ms = 0.0;
+    int variant = -1;
+    int graph_nodes = 0;
+};
+
+static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
+    hipStream_t st = ctx->stream;
+    const Pattern *PM = rq.PM, *PK = rq.PK;
+    const int b = PK->b, dtype = rq.dtype, n_pl = rq.n_pl;
+    const std::vector<int32_t> &row0 = *rq.row0;
+    const int nsys = (int)row0.size() - 1;
+    const size_t esz = dtype == 1 ? 4 : 8;
+    const EmbedMap *emb = get_embed(ctx, PM, PK, "M~ in the chain pattern");
+    const std::vector<int32_t> breaks(row0.begin(), row0.end() - 1);
+    ListedPlan *lp = get_listed_plan(ctx, PK, PM, PK, dtype, breaks);
+    if (!lp->usable) CHESS_THROW(CHESS_E_UNSUPPORTED, "batched chain: rows too long for the listed product");
+    const size_t tb = vbytes(PK, dtype);
+    DevBuf U0(tb), U1(tb), Bt(vbytes(PM, dtype) + 16384);
+    HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, PM->d_tmap.as<int64_t>(), rq.Mt, Bt.p, 1, st));
+    HIPCHECK(launch_fill_identity(dtype, b, PK->nnzb, PK->d_brow.as<int32_t>(), PK->d_ci.as<int32_t>(), U0.p, st));
+    HIPCHECK(launch_zero(U1.p, tb, st));
+    HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, emb->d_map_t.as<int64_t>(), rq.Mt, U1.p, 1, st));
+    select_listed_variant(ctx, lp, dtype, n_pl, U1.p, Bt.p, U0.p);
+    rq.variant = lp->dev.variant;
+    DevBuf dcoef(sizeof(double) * (size_t)std::max(rq.nq, 1) * n_pl * nsys);
+    if (rq.nq)
+        HIPCHECK(hipMemcpyAsync(dcoef.p, rq.coef_tab, sizeof(double) * (size_t)rq.nq * n_pl * nsys, hipMemcpyHostToDevice, st));
+    // sum' starts: acc = c_0 / 2 T_0 + c_1 T_1, system by system (contiguous ranges)
+    for (int sy = 0; sy < nsys; ++sy) {
+        const int64_t off = PK->rp[row0[sy]] * b * b;
+        const int64_t len = (PK->rp[row0[sy + 1]] - PK->rp[row0[sy]]) * b * b;
+        for (int q = 0; q < rq.nq; ++q) {
+            const double *c = rq.coef_tab + (size_t)q * n_pl * nsys;
+            HIPCHECK(launch_axpby_to_f64(dtype, len, 0.5 * c[sy], (const char *)U0.p + off * esz,
+                                         n_pl > 1 ? c[nsys + sy] : 0.0, (const char *)U1.p + off * esz,
+                                         rq.acc[q] + off, st));
+        }
+    }
+    const int ntiles = lp->dev.ntiles;
+    std::vector<int32_t> seg(nsys + 1);
+    {
+        int t = 0;
+        for (int sy = 0; sy <= nsys; ++sy) {
+            while (t < ntiles && lp->tile_row0[t] < row0[sy]) ++t;
+            seg[sy] = t;
+        }
+    }
+    DevBuf dseg;
+    upload(dseg, seg, st);
+    DevBuf part(sizeof(double) * (size_t)std::max(n_pl, 2) * std::max(ntiles, 256));
+    DevBuf mom(sizeof(double) * (size_t)std::max(n_pl, 2) * nsys);
+    double *pd = part.as<double>();
+    const int tparts = 256;
+    for (int sy = 0; sy < nsys; ++sy) {
+        const int nbs = row0[sy + 1] - row0[sy];
+        const int64_t *dg = PK->d_diag.as<int64_t>() + row0[sy];
+        HIPCHECK(launch_trace(dtype, b, nbs, dg, U0.p, pd, tparts, st));
+        HIPCHECK(launch_reduce_rows(1, tparts, pd, mom.as<double>() + sy, st));
+        HIPCHECK(launch_trace(dtype, b, nbs, dg, U1.p, pd, tparts, st));
+        HIPCHECK(launch_reduce_rows(1, tparts, pd, mom.as<double>() + nsys + sy, st));
+    }
+    void *ucur = U1.p, *uprev = U0.p;
+    auto step = [&](int k) {
+        Epilogue ep;
+        ep.alpha = 2.0;
+        ep.beta = -1.0;
+        ep.prev = uprev;
+        ep.nacc = rq.nq;
+        ep.row_sys = rq.d_row_sys;
+        for (int q = 0; q < rq.nq; ++q) {
+            ep.acc[q] = rq.acc[q];
+            ep.coef_sys[q] = dcoef.as<double>() + ((size_t)q * n_pl + k + 1) * nsys;
+        }
+        ep.trace_partial = pd + (size_t)(k + 1) * ntiles;
+        product_listed(ctx, dtype, lp, ucur, Bt.p, uprev, ep);
+        std::swap(ucur, uprev);
+    };
+    Timer tm(st);
+    tm.start();
+    if (n_pl > 2) step(1);  // eager: also settles per-kernel attributes before recording
+    if (n_pl > 3) {
+        if (rq.use_graph) {
+            if (!ctx->capture_stream) HIPCHECK(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            ctx->stream = ctx->capture_stream;  // the products are recorded, not run
+            try {
+                HIPCHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+                for (int k = 2; k + 1 < n_pl; ++k) step(k);
+                HIPCHECK(hipStreamEndCapture(ctx->stream, &graph));
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(ctx->stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                ctx->stream = st;
+                throw;
+            }
+            ctx->stream = st;
+            size_t nn = 0;
+            (void)hipGraphGetNodes(graph, nullptr, &nn);
+            rq.graph_nodes = (int)nn;
+            hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (e == hipSuccess) e = hipGraphLaunch(exec, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (exec) (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            HIPCHECK(e);
+        } else {
+            for (int k = 2; k + 1 < n_pl; ++k) step(k);
+        }
+    }
+    rq.kernel_ms = tm.stop();
+    if (n_pl > 2)
+        HIPCHECK(launch_segment_sum(n_pl - 2, ntiles, nsys, dseg.as<int32_t>(), pd + 2 * (size_t)ntiles,
+                                    mom.as<double>() + 2 * (size_t)nsys, st));
+    if (rq.moments) {
+        rq.moments->assign((size_t)n_pl * nsys, 0.0);
+        HIPCHECK(hipMemcpyAsync(rq.moments->data(), mom.p, sizeof(double) * (size_t)n_pl * nsys, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+}
+
 // ---------------------------------------------------------------------------
 // option handling
 // ---------------------------------------------------------------------------
@@ -847,6 +1014,9 @@ static chess_opts resolve_opts(const chess_opts *o) {
     if (o) r = *o;
     if (r.precision != CHESS_F64 && r.precision != CHESS_F32) CHESS_THROW(CHESS_E_UNSUPPORTED, "precision %d", r.precision);
     if (r.smearing != CHESS_ERFC && r.smearing != CHESS_FERMI_DIRAC) CHESS_THROW(CHESS_E_ARG, "smearing %d", r.smearing);
+    if (r.bounds_mode != CHESS_BOUNDS_GERSHGORIN && r.bounds_mode != CHESS_BOUNDS_LANCZOS &&
+        r.bounds_mode != CHESS_BOUNDS_LEARNED)
+        CHESS_THROW(CHESS_E_ARG, "bounds_mode %d", r.bounds_mode);
     const double deftol = r.precision == CHESS_F64 ? 1e-10 : 1e-6;
     if (!(r.tol_fit > 0)) r.tol_fit = deftol;
     if (!(r.tol_fit_s > 0)) r.tol_fit_s = deftol;
@@ -1016,6 +1186,115 @@ static void h_bounds(chess_ctx *ctx, const Pattern *PH, const double *Hp, const 
     if (!(*hi > *lo)) CHESS_THROW(CHESS_E_ARG, "empty spectral interval [%g, %g]", *lo, *hi);
 }
 
+// ---------------------------------------------------------------------------
+// learned predictor: features of H', network inference
+// ---------------------------------------------------------------------------
+
+// The 64 features (all from H' on its pattern, cheap next to the chain):
+//   0 c, 1 w (centre and half width of the Gershgorin interval of H'),
+//   2-3 bounds of S, 4 kT, 5 kT / w, 6 N_e / n, 7 log n, 8 b / 9,
+//   9-16 t_k / n, k = 1..8, moments Tr T_k((H' - c) / w) from 7 chain steps,
+//   17-40 histogram of the diagonal (d - c) / w over [-1, 1] (fractions),
+//   41-56 histogram of the Gershgorin radii R / w over [0, 1] (fractions),
+//   57-58 mean and standard deviation of (d - c) / w, 59-60 mean and max of
+//   R / w, 61-62 min and max of (d - c) / w,
+//   63 (mu_0 - c) / w with mu_0 solving N(mu) = N_e for the 9-term expansion
+//      of a broad occupation (kT = w / 4) from the same moments.
+struct Features {
+    float f[kMlpIn];
+    double g_lo = 0, g_hi = 0;
+};
+
+static void compute_features(chess_ctx *ctx, const Pattern *PH, const double *Hp, const Pattern *PK,
+                             double s_lo, double s_hi, double n_e, double kT, Features &fe) {
+    static_assert(kMlpIn == 64 && kDiagBins == 24 && kRadBins == 16, "feature layout");
+    hipStream_t st = ctx->stream;
+    const int b = PH->b;
+    const int64_t n = PH->n();
+    double g_lo, g_hi;
+    gershgorin(ctx, PH, Hp, &g_lo, &g_hi);
+    const double c = 0.5 * (g_lo + g_hi), w = 0.5 * (g_hi - g_lo);
+    if (!(w > 0)) CHESS_THROW(CHESS_E_ARG, "features: Gershgorin interval of H' is empty");
+    const int parts = row_feature_parts(b, PH->nb);
+    DevBuf hist(sizeof(uint32_t) * (kDiagBins + kRadBins)), part(sizeof(double) * 6 * (size_t)parts);
+    HIPCHECK(launch_zero(hist.p, hist.bytes, st));
+    HIPCHECK(launch_row_features(b, PH->nb, PH->d_rp.as<int64_t>(), PH->d_ci.as<int32_t>(), Hp, c, w,
+                                 hist.as<uint32_t>(), part.as<double>(), st));
+    std::vector<uint32_t> hh(kDiagBins + kRadBins);
+    std::vector<double> pp(6 * (size_t)parts);
+    HIPCHECK(hipMemcpyAsync(hh.data(), hist.p, hist.bytes, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(pp.data(), part.p, pp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    // moments of (H' - c) / w
+    DevBuf Ht(sizeof(double) * (size_t)PH->nnzb * b * b);
+    HIPCHECK(launch_scale_shift(b, PH->nnzb, PH->d_brow.as<int32_t>(), PH->d_ci.as<int32_t>(), Hp,
+                                Ht.as<double>(), 1.0 / w, c, st));
+    std::vector<double> mom;
+    ChainRequest rq;
+    rq.label = "feature moments";
+    rq.PM = PH;
+    rq.Mt = Ht.as<double>();
+    rq.PK = PK;
+    rq.n_pl = 9;
+    rq.dtype = 0;
+    rq.moments = &mom;
+    run_chain(ctx, rq);  // synchronises the stream
+    double sd = 0, sd2 = 0, sr = 0, mr = -1e300, mnd = 1e300, mxd = -1e300;
+    for (int q = 0; q < parts; ++q) {
+        const double *o = &pp[6 * (size_t)q];
+        sd += o[0];
+        sd2 += o[1];
+        sr += o[2];
+        mr = std::max(mr, o[3]);
+        mnd = std::min(mnd, o[4]);
+        mxd = std::max(mxd, o[5]);
+    }
+    const double dn = (double)n;
+    hostmath::CountFunction N;
+    N.init(mom, g_lo, g_hi, 0.25 * w, 0);
+    double mu0 = c;
+    int it = 0;
+    if (!hostmath::bisect_mu(N, n_e, 1e-9 * std::max(1.0, n_e), g_lo - 4 * w, g_hi + 4 * w, &mu0, &it)) mu0 = c;
+    float *f = fe.f;
+    f[0] = (float)c;
+    f[1] = (float)w;
+    f[2] = (float)s_lo;
+    f[3] = (float)s_hi;
+    f[4] = (float)kT;
+    f[5] = (float)(kT / w);
+    f[6] = (float)(n_e / dn);
+    f[7] = (float)std::log(dn);
+    f[8] = (float)(b / 9.0);
+    for (int k = 1; k <= 8; ++k) f[8 + k] = (float)(mom[k] / dn);
+    for (int q = 0; q < kDiagBins; ++q) f[17 + q] = (float)(hh[q] / dn);
+    for (int q = 0; q < kRadBins; ++q) f[41 + q] = (float)(hh[kDiagBins + q] / dn);
+    const double mean_d = sd / dn;
+    f[57] = (float)mean_d;
+    f[58] = (float)std::sqrt(std::max(0.0, sd2 / dn - mean_d * mean_d));
+    f[59] = (float)(sr / dn);
+    f[60] = (float)mr;
+    f[61] = (float)mnd;
+    f[62] = (float)mxd;
+    f[63] = (float)((mu0 - c) / w);
+    fe.g_lo = g_lo;
+    fe.g_hi = g_hi;
+}
+
+// Network outputs for one feature vector, mapped back to energies:
+// out = {eps_min, eps_max, mu} = c + w * y.
+static void predict(chess_ctx *ctx, const Features &fe, double out[3]) {
+    if (!ctx->model.loaded) CHESS_THROW(CHESS_E_ARG, "no model loaded (chess_model_load)");
+    hipStream_t st = ctx->stream;
+    DevBuf x(sizeof(float) * kMlpIn), y(sizeof(float) * kMlpOut);
+    HIPCHECK(hipMemcpyAsync(x.p, fe.f, sizeof(float) * kMlpIn, hipMemcpyHostToDevice, st));
+    HIPCHECK(launch_mlp_forward(ctx->model.params.as<float>(), ctx->model.norm.as<float>(), x.as<float>(),
+                                1, nullptr, y.as<float>(), st));
+    float yh[kMlpOut];
+    HIPCHECK(hipMemcpyAsync(yh, y.p, sizeof(yh), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    const double c = 0.5 * (fe.g_lo + fe.g_hi), w = 0.5 * (fe.g_hi - fe.g_lo);
+    for (int q = 0; q < kMlpOut; ++q) out[q] = c + w * (double)yh[q];
+}
+
 static hostmath::Fn occupation(int smearing, double mu, double kT) {
     if (smearing == CHESS_ERFC) return [mu, kT](double e) { return hostmath::occ_erfc(e, mu, kT); };
     return [mu, kT](double e) { return hostmath::occ_fd(e, mu, kT); };
@@ -1049,6 +1328,7 @@ static void fill_info_defaults(chess_info *info) {
     const double nan = std::numeric_limits<double>::quiet_NaN();
     info->mu = info->lo = info->hi = info->s_lo = info->s_hi = nan;
     info->tr_ks = info->ne_chain = info->penalty = nan;
+    info->pred_lo = info->pred_hi = info->pred_mu = nan;
     info->kernel_variant = -1;
 }
 
@@ -1080,7 +1360,41 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     const int dtype = o.precision;
     const int64_t nK = PK->nnzb * b * b;
     double lo, hi;
-    h_bounds(ctx, PH, F.Hp.as<double>(), o, &lo, &hi);
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    const bool given = std::isfinite(o.bounds[0]) && std::isfinite(o.bounds[1]);
+    bool learned = false;
+    int fallback = 0;
+    double pred[3] = {nan, nan, nan};
+    double br[2] = {o.mu_bracket[0], o.mu_bracket[1]};
+    const bool br_given = std::isfinite(br[0]) && std::isfinite(br[1]);
+    Features fe;
+    double ms_learned = 0.0;
+    if (!given && o.bounds_mode == CHESS_BOUNDS_LEARNED) {
+        // predicted bounds widened by the model's margins (never beyond the
+        // Gershgorin interval) and a predicted mu bracket; Eq. 6 and the
+        // growth test still judge the bounds, bisection still judges mu
+        const double t0 = now_ms();
+        compute_features(ctx, PH, F.Hp.as<double>(), PK, F.s.lo, F.s.hi, n_e, kT, fe);
+        predict(ctx, fe, pred);
+        const Model &M = ctx->model;
+        const double w = 0.5 * (fe.g_hi - fe.g_lo);
+        lo = std::max(fe.g_lo, pred[0] - M.margin_lo * w);
+        hi = std::min(fe.g_hi, pred[1] + M.margin_hi * w);
+        if (hi > lo) {
+            learned = true;
+        } else {
+            lo = fe.g_lo;
+            hi = fe.g_hi;
+            fallback |= 1;
+        }
+        if (!br_given) {
+            br[0] = pred[2] - M.mu_half * w;
+            br[1] = pred[2] + M.mu_half * w;
+        }
+        ms_learned = now_ms() - t0;
+    } else {
+        h_bounds(ctx, PH, F.Hp.as<double>(), o, &lo, &hi);
+    }
 
     DevBuf Ht(sizeof(double) * (size_t)PH->nnzb * b * b);
     DevBuf accK(sizeof(double) * (size_t)nK);
@@ -1145,6 +1459,15 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         if (pen_valid && std::fabs(penalty) > 0.5) ok = false;
         if (!pen_valid) penalty = std::numeric_limits<double>::quiet_NaN();
         if (ok) break;
+        if (learned) {
+            // predicted bounds rejected: fall back to the rigorous interval
+            lo = fe.g_lo;
+            hi = fe.g_hi;
+            learned = false;
+            fallback |= 1;
+            reexp++;
+            continue;
+        }
         if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "spectral bounds [%g, %g] still fail after %d widenings", lo, hi, attempt);
         const double w = hi - lo;
         // Eq. 6 sign tells which side: positive -> an eigenvalue below lo
@@ -1167,8 +1490,10 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     if (!std::isfinite(mu)) {
         const double tol_ne = o.tol_ne > 0 ? o.tol_ne : 1e-8 * n_e;
         bool found = false;
-        if (std::isfinite(o.mu_bracket[0]) && std::isfinite(o.mu_bracket[1]))
-            found = hostmath::bisect_mu(N, n_e, tol_ne, o.mu_bracket[0], o.mu_bracket[1], &mu, &iters);
+        if (std::isfinite(br[0]) && std::isfinite(br[1])) {
+            found = hostmath::bisect_mu(N, n_e, tol_ne, br[0], br[1], &mu, &iters);
+            if (!found && !br_given) fallback |= 2;
+        }
         if (!found) {
             int it2 = 0;
             found = hostmath::bisect_mu(N, n_e, tol_ne, lo - 20 * kT, hi + 20 * kT, &mu, &it2);
@@ -1236,6 +1561,11 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         info->ms_post = t_end - t_post0;
         info->ms_chain_kernel = kernel_ms;
         info->kernel_variant = variant;
+        info->pred_lo = pred[0];
+        info->pred_hi = pred[1];
+        info->pred_mu = pred[2];
+        info->fallback = fallback;
+        info->ms_learned = ms_learned;
     }
 }
 
@@ -1408,6 +1738,396 @@ static void masked_product_api(chess_ctx *ctx, const chess_matrix *A, const ches
     HIPCHECK(hipStreamSynchronize(ctx->stream));
 }
 
+// ---------------------------------------------------------------------------
+// batches of independent systems
+// ---------------------------------------------------------------------------
+
+// Block-diagonal concatenation of patterns (all with block edge b).
+static const Pattern *concat_patterns(chess_ctx *ctx, const std::vector<const Pattern *> &ps,
+                                      const char *what) {
+    const int b = ps[0]->b;
+    int nb = 0;
+    int64_t nnzb = 0;
+    for (const Pattern *p : ps) {
+        nb += p->nb;
+        nnzb += p->nnzb;
+    }
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    rp.reserve((size_t)nb + 1);
+    ci.reserve((size_t)nnzb);
+    rp.push_back(0);
+    int r0 = 0;
+    int64_t z0 = 0;
+    for (const Pattern *p : ps) {
+        for (int i = 0; i < p->nb; ++i) rp.push_back(z0 + p->rp[i + 1]);
+        for (int32_t c : p->ci) ci.push_back(c + r0);
+        r0 += p->nb;
+        z0 += p->nnzb;
+    }
+    return get_pattern_host(ctx, b, nb, nnzb, std::move(rp), std::move(ci), what);
+}
+
+// One group of systems with the same block edge: every step of the
+// single-system method, with the chains and the sandwich products run once
+// over the block-diagonal concatenation.
+static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const chess_batch_item *items,
+                          const chess_opts &o, bool use_graph, double *ms_chains) {
+    hipStream_t st = ctx->stream;
+    const int nsys = (int)idx.size();
+    const int dtype = o.precision;
+    std::vector<const Pattern *> PHs, PSs, PKs;
+    for (int i : idx) {
+        const chess_batch_item &it = items[i];
+        const Pattern *PH = get_pattern(ctx, &it.H->pat, "H pattern");
+        const Pattern *PS = get_pattern(ctx, &it.S->pat, "S pattern");
+        const Pattern *PK = get_pattern(ctx, it.pattern, "kernel pattern");
+        if (PH->nb != PK->nb || PS->nb != PK->nb || PH->b != PK->b || PS->b != PK->b)
+            CHESS_THROW(CHESS_E_ARG, "system %d: H, S and the pattern differ in size or block edge", i);
+        get_embed(ctx, PH, PK, "H in the kernel pattern");
+        get_embed(ctx, PS, PK, "S in the kernel pattern");
+        for (int q = 0; q < 3; ++q)
+            if (it.K_out[q]) {
+                check_matrix(it.K_out[q], "K_out");
+                require_same(get_pattern(ctx, &it.K_out[q]->pat, "K_out pattern"), PK, "K_out");
+            }
+        if (it.Sinvhalf_out) require_same(get_pattern(ctx, &it.Sinvhalf_out->pat, "Sinvhalf_out pattern"), PK, "Sinvhalf_out");
+        if (it.Sinv_out) require_same(get_pattern(ctx, &it.Sinv_out->pat, "Sinv_out pattern"), PK, "Sinv_out");
+        PHs.push_back(PH);
+        PSs.push_back(PS);
+        PKs.push_back(PK);
+    }
+    const int b = PKs[0]->b;
+    const int64_t bb = (int64_t)b * b;
+    const Pattern *PH = concat_patterns(ctx, PHs, "batched H pattern");
+    const Pattern *PS = concat_patterns(ctx, PSs, "batched S pattern");
+    const Pattern *PK = concat_patterns(ctx, PKs, "batched kernel pattern");
+    std::vector<int32_t> row0(nsys + 1, 0), row_sys((size_t)PK->nb);
+    std::vector<int64_t> offH(nsys + 1, 0), offS(nsys + 1, 0), offK(nsys + 1, 0);
+    for (int s = 0; s < nsys; ++s) {
+        row0[s + 1] = row0[s] + PKs[s]->nb;
+        offH[s + 1] = offH[s] + PHs[s]->nnzb;
+        offS[s + 1] = offS[s] + PSs[s]->nnzb;
+        offK[s + 1] = offK[s] + PKs[s]->nnzb;
+        for (int r = row0[s]; r < row0[s + 1]; ++r) row_sys[r] = s;
+    }
+    DevBuf d_row_sys;
+    upload(d_row_sys, row_sys, st);
+    DevBuf Hs(sizeof(double) * (size_t)PH->nnzb * bb), Ss(sizeof(double) * (size_t)PS->nnzb * bb);
+    for (int s = 0; s < nsys; ++s) {
+        const chess_batch_item &it = items[idx[s]];
+        HIPCHECK(hipMemcpyAsync(Hs.as<double>() + offH[s] * bb, it.H->val, sizeof(double) * PHs[s]->nnzb * bb, hipMemcpyDeviceToDevice, st));
+        HIPCHECK(hipMemcpyAsync(Ss.as<double>() + offS[s] * bb, it.S->val, sizeof(double) * PSs[s]->nnzb * bb, hipMemcpyDeviceToDevice, st));
+    }
+    // S bounds per system, then one S chain for x^-1/2 and x^-1
+    std::vector<double> slo(nsys), shi(nsys), ssig(nsys), stau(nsys);
+    std::vector<int> npls(nsys);
+    int npls_max = 2;
+    for (int s = 0; s < nsys; ++s) {
+        s_bounds(ctx, PSs[s], (const double *)items[idx[s]].S->val, o, true, &slo[s], &shi[s]);
+        hostmath::scale_shift(slo[s], shi[s], &ssig[s], &stau[s]);
+        int m = o.n_pl_s;
+        if (m <= 0) {
+            m = 1;
+            for (double a : {-0.5, -1.0}) {
+                const int d = hostmath::degree([a](double x) { return std::pow(x, a); }, slo[s], shi[s], o.tol_fit_s, 8, 20000, 2048);
+                if (d < 0) CHESS_THROW(CHESS_E_NOCONV, "system %d: no degree reaches tol_fit_s", idx[s]);
+                m = std::max(m, d);
+            }
+        }
+        npls[s] = m;
+        npls_max = std::max(npls_max, m);
+    }
+    auto coef_table = [&](int nq, int n_pl, const std::vector<int> &own, auto &&fn) {
+        std::vector<double> tab((size_t)nq * n_pl * nsys, 0.0);
+        for (int s = 0; s < nsys; ++s)
+            for (int q = 0; q < nq; ++q) {
+                const std::vector<double> c = fn(s, q, own[s]);
+                for (int k = 0; k < own[s]; ++k) tab[((size_t)q * n_pl + k) * nsys + s] = c[k];
+            }
+        return tab;
+    };
+    DevBuf dsig(sizeof(double) * nsys), dtau(sizeof(double) * nsys);
+    HIPCHECK(hipMemcpyAsync(dsig.p, ssig.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(dtau.p, stau.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, st));
+    DevBuf St(Ss.bytes);
+    HIPCHECK(launch_scale_shift_rows(b, PS->nnzb, PS->d_brow.as<int32_t>(), PS->d_ci.as<int32_t>(), d_row_sys.as<int32_t>(),
+                                     dsig.as<double>(), dtau.as<double>(), Ss.as<double>(), St.as<double>(), st));
+    const std::vector<double> stab = coef_table(2, npls_max, npls, [&](int s, int q, int m) {
+        const double a = q == 0 ? -0.5 : -1.0;
+        return hostmath::cheb_coeffs([a](double x) { return std::pow(x, a); }, slo[s], shi[s], m);
+    });
+    const size_t kbytes = sizeof(double) * (size_t)PK->nnzb * bb;
+    Frame F;
+    F.accX.alloc(kbytes);
+    DevBuf accSinv(kbytes);
+    std::vector<double> smom;
+    BatchChain sc;
+    sc.PM = PS;
+    sc.PK = PK;
+    sc.Mt = St.as<double>();
+    sc.n_pl = npls_max;
+    sc.nq = 2;
+    sc.dtype = dtype;
+    sc.coef_tab = stab.data();
+    sc.acc[0] = F.accX.as<double>();
+    sc.acc[1] = accSinv.as<double>();
+    sc.row0 = &row0;
+    sc.d_row_sys = d_row_sys.as<int32_t>();
+    sc.use_graph = use_graph;
+    sc.moments = &smom;
+    run_chain_batched(ctx, sc);
+    St.release();
+    for (int s = 0; s < nsys; ++s) {
+        std::vector<double> t(npls[s]);
+        for (int k = 0; k < npls[s]; ++k) t[k] = smom[(size_t)k * nsys + s];
+        if (!growth_ok(t, PKs[s]->n())) CHESS_THROW(CHESS_E_BOUNDS, "system %d: bounds of S fail the growth test", idx[s]);
+    }
+    // H' = sym(P_H o (X P_K o (H X))) over the whole batch
+    {
+        DevBuf ZT(kbytes);
+        product(ctx, 0, get_plan(ctx, PK, PH, PK, 0), F.accX.p, Hs.p, ZT.p, Epilogue{});
+        F.X.alloc(kbytes);
+        transpose_into(ctx, PK, F.accX.as<double>(), F.X.as<double>());
+        DevBuf Hraw(Hs.bytes);
+        product(ctx, 0, get_plan(ctx, PK, PK, PH, 0), F.X.p, ZT.p, Hraw.p, Epilogue{});
+        F.Hp.alloc(Hs.bytes);
+        HIPCHECK(launch_symmetrize(b, PH->nnzb, PH->d_tmap.as<int64_t>(), Hraw.as<double>(), F.Hp.as<double>(), st));
+    }
+    // bounds, degree and trial mu per system
+    std::vector<double> lo(nsys), hi(nsys), hsig(nsys), htau(nsys), kTs(nsys), nes(nsys);
+    std::vector<std::array<double, 3>> mus(nsys), preds(nsys);
+    std::vector<int> npl(nsys);
+    int npl_max = 2;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    for (int s = 0; s < nsys; ++s) {
+        const chess_batch_item &it = items[idx[s]];
+        const double *Hp = F.Hp.as<double>() + offH[s] * bb;
+        kTs[s] = it.kT;
+        nes[s] = it.n_electrons;
+        preds[s] = {nan, nan, nan};
+        double mu_half = 0.0;
+        if (!(std::isfinite(o.bounds[0]) && std::isfinite(o.bounds[1])) && o.bounds_mode == CHESS_BOUNDS_LEARNED) {
+            Features fe;
+            compute_features(ctx, PHs[s], Hp, PKs[s], slo[s], shi[s], it.n_electrons, it.kT, fe);
+            double pr[3];
+            predict(ctx, fe, pr);
+            const double w = 0.5 * (fe.g_hi - fe.g_lo);
+            lo[s] = std::max(fe.g_lo, pr[0] - ctx->model.margin_lo * w);
+            hi[s] = std::min(fe.g_hi, pr[1] + ctx->model.margin_hi * w);
+            if (!(hi[s] > lo[s])) {
+                lo[s] = fe.g_lo;
+                hi[s] = fe.g_hi;
+            }
+            preds[s] = {pr[0], pr[1], pr[2]};
+            mu_half = ctx->model.mu_half * w;
+        } else {
+            h_bounds(ctx, PHs[s], Hp, o, &lo[s], &hi[s]);
+        }
+        for (int q = 0; q < 3; ++q) {
+            double m = it.mu_trial[q];
+            if (!std::isfinite(m)) {
+                if (!std::isfinite(preds[s][2]))
+                    CHESS_THROW(CHESS_E_ARG, "system %d: mu_trial[%d] not given and no prediction (CHESS_BOUNDS_LEARNED)", idx[s], q);
+                m = preds[s][2] + (q - 1) * mu_half;
+            }
+            mus[s][q] = m;
+        }
+        hostmath::scale_shift(lo[s], hi[s], &hsig[s], &htau[s]);
+        int m = o.n_pl;
+        if (m <= 0) {
+            m = hostmath::degree(occupation(o.smearing, htau[s], it.kT), lo[s], hi[s], o.tol_fit, 8, 20000, 2048);
+            if (m < 0) CHESS_THROW(CHESS_E_NOCONV, "system %d: no degree up to 20000 reaches tol_fit", idx[s]);
+        }
+        npl[s] = m;
+        npl_max = std::max(npl_max, m);
+    }
+    HIPCHECK(hipMemcpyAsync(dsig.p, hsig.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(dtau.p, htau.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, st));
+    DevBuf Ht(Hs.bytes);
+    HIPCHECK(launch_scale_shift_rows(b, PH->nnzb, PH->d_brow.as<int32_t>(), PH->d_ci.as<int32_t>(), d_row_sys.as<int32_t>(),
+                                     dsig.as<double>(), dtau.as<double>(), F.Hp.as<double>(), Ht.as<double>(), st));
+    const std::vector<double> htab = coef_table(3, npl_max, npl, [&](int s, int q, int m) {
+        return hostmath::cheb_coeffs(occupation(o.smearing, mus[s][q], kTs[s]), lo[s], hi[s], m);
+    });
+    DevBuf accK[3];
+    for (auto &a : accK) a.alloc(kbytes);
+    std::vector<double> hmom;
+    BatchChain hc;
+    hc.PM = PH;
+    hc.PK = PK;
+    hc.Mt = Ht.as<double>();
+    hc.n_pl = npl_max;
+    hc.nq = 3;
+    hc.dtype = dtype;
+    hc.coef_tab = htab.data();
+    for (int q = 0; q < 3; ++q) hc.acc[q] = accK[q].as<double>();
+    hc.row0 = &row0;
+    hc.d_row_sys = d_row_sys.as<int32_t>();
+    hc.use_graph = use_graph;
+    hc.moments = &hmom;
+    run_chain_batched(ctx, hc);
+    *ms_chains += sc.kernel_ms + hc.kernel_ms;
+    Ht.release();
+    // per system: Eq. 6 and growth checks, mu from the moments, N at the trial mu
+    std::vector<double> mu_star(nsys), ne_tr(3 * (size_t)nsys), pen(nsys);
+    std::vector<int> iters(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        std::vector<double> t(npl[s]);
+        for (int k = 0; k < npl[s]; ++k) t[k] = hmom[(size_t)k * nsys + s];
+        double fit_err = 1.0;
+        const double p = hostmath::penalty_trace(t, -200.0, &fit_err);
+        const bool pen_valid = fit_err * (double)PKs[s]->n() < 0.1;
+        pen[s] = pen_valid ? p : nan;
+        if (!growth_ok(t, PKs[s]->n()) || (pen_valid && std::fabs(p) > 0.5))
+            CHESS_THROW(CHESS_E_BOUNDS, "system %d: bounds [%g, %g] fail Eq. 6 or the growth test", idx[s], lo[s], hi[s]);
+        hostmath::CountFunction N;
+        N.init(t, lo[s], hi[s], kTs[s], o.smearing == CHESS_ERFC ? 0 : 1);
+        const double tol_ne = o.tol_ne > 0 ? o.tol_ne : 1e-8 * nes[s];
+        double m = nan;
+        int itn = 0;
+        if (!hostmath::bisect_mu(N, nes[s], tol_ne, lo[s] - 20 * kTs[s], hi[s] + 20 * kTs[s], &m, &itn))
+            CHESS_THROW(CHESS_E_NOCONV, "system %d: N(mu) does not bracket %g electrons", idx[s], nes[s]);
+        mu_star[s] = m;
+        iters[s] = itn;
+        for (int q = 0; q < 3; ++q) ne_tr[3 * (size_t)s + q] = N(mus[s][q]);
+    }
+    // K at the trial mu: K = P_K o (X P_K o (K' X)) over the batch, then per system
+    DevBuf Kb(kbytes);
+    const int nparts = 256;
+    DevBuf part(sizeof(double) * (nparts + 1));
+    for (int q = 0; q < 3; ++q) {
+        bool any = false;
+        for (int s = 0; s < nsys; ++s) any = any || items[idx[s]].K_out[q];
+        if (!any) continue;
+        post_transform(ctx, PK, F, accK[q].as<double>(), PS, Ss.as<double>(), Kb.as<double>());
+        for (int s = 0; s < nsys; ++s) {
+            chess_matrix *Ko = items[idx[s]].K_out[q];
+            if (!Ko) continue;
+            HIPCHECK(hipMemcpyAsync(Ko->val, Kb.as<double>() + offK[s] * bb, sizeof(double) * PKs[s]->nnzb * bb, hipMemcpyDeviceToDevice, st));
+            if (q == 1 && items[idx[s]].info) {
+                const EmbedMap *es = get_embed(ctx, PSs[s], PKs[s], "S in the kernel pattern");
+                HIPCHECK(launch_trace_product(b, PSs[s]->nnzb, es->d_map_t.as<int64_t>(), (const double *)Ko->val,
+                                              (const double *)items[idx[s]].S->val, part.as<double>(), nparts, st));
+                HIPCHECK(launch_reduce_rows(1, nparts, part.as<double>(), part.as<double>() + nparts, st));
+                double tr = 0.0;
+                HIPCHECK(hipMemcpyAsync(&tr, part.as<double>() + nparts, sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPCHECK(hipStreamSynchronize(st));
+                items[idx[s]].info->tr_ks = tr;
+            }
+        }
+    }
+    // S^-1/2 = X and S^-1 (the accumulators hold the transposes)
+    DevBuf Sinv(kbytes);
+    transpose_into(ctx, PK, accSinv.as<double>(), Sinv.as<double>());
+    for (int s = 0; s < nsys; ++s) {
+        const chess_batch_item &it = items[idx[s]];
+        const size_t bytes = sizeof(double) * PKs[s]->nnzb * bb;
+        if (it.Sinvhalf_out) HIPCHECK(hipMemcpyAsync(it.Sinvhalf_out->val, F.X.as<double>() + offK[s] * bb, bytes, hipMemcpyDeviceToDevice, st));
+        if (it.Sinv_out) HIPCHECK(hipMemcpyAsync(it.Sinv_out->val, Sinv.as<double>() + offK[s] * bb, bytes, hipMemcpyDeviceToDevice, st));
+        if (it.ne_trial)
+            for (int q = 0; q < 3; ++q) it.ne_trial[q] = ne_tr[3 * (size_t)s + q];
+        if (chess_info *info = it.info) {
+            info->mu = mu_star[s];
+            info->lo = lo[s];
+            info->hi = hi[s];
+            info->s_lo = slo[s];
+            info->s_hi = shi[s];
+            info->ne_chain = ne_tr[3 * (size_t)s + 1];
+            info->penalty = pen[s];
+            info->n_pl = npl[s];
+            info->n_pl_s = npls[s];
+            info->passes = 1;
+            info->bisect_iters = iters[s];
+            info->chain_steps = std::max(npl_max - 2, 0) + std::max(npls_max - 2, 0);
+            info->kernel_variant = hc.variant;
+            info->pred_lo = preds[s][0];
+            info->pred_hi = preds[s][1];
+            info->pred_mu = preds[s][2];
+        }
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+}
+
+static void fermi_batched(chess_ctx *ctx, int32_t nsys, const chess_batch_item *items,
+                          const chess_opts *opts) {
+    const double t0 = now_ms();
+    chess_opts o = resolve_opts(opts);
+    if (nsys <= 0 || !items) CHESS_THROW(CHESS_E_ARG, "empty batch");
+    std::vector<int> by4, by9;
+    for (int i = 0; i < nsys; ++i) {
+        const chess_batch_item &it = items[i];
+        check_matrix(it.H, "H");
+        check_matrix(it.S, "S");
+        if (!it.pattern) CHESS_THROW(CHESS_E_ARG, "system %d: null pattern", i);
+        if (!(it.kT > 0)) CHESS_THROW(CHESS_E_ARG, "system %d: kT must be positive", i);
+        fill_info_defaults(it.info);
+        (it.pattern->b == 4 ? by4 : by9).push_back(i);
+    }
+    // CHESS_BATCH_GRAPH=0 in the environment runs the products without graph capture
+    bool use_graph = true;
+    if (const char *env = std::getenv("CHESS_BATCH_GRAPH")) use_graph = std::strcmp(env, "0") != 0;
+    double ms_chains = 0.0;
+    if (!by4.empty()) batched_group(ctx, by4, items, o, use_graph, &ms_chains);
+    if (!by9.empty()) batched_group(ctx, by9, items, o, use_graph, &ms_chains);
+    const double ms = now_ms() - t0;
+    for (int i = 0; i < nsys; ++i)
+        if (items[i].info) {
+            items[i].info->ms_total = ms;
+            items[i].info->ms_chain_kernel = ms_chains;
+        }
+}
+
+// Features of the generalized problem (H, S) for the learned predictor: the
+// orthogonal frame as in the Fermi operator, then compute_features.
+static void features_api(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
+                         const chess_pattern *pattern, double n_e, double kT, float *feat,
+                         double *gersh, const chess_opts *opts) {
+    chess_opts o = resolve_opts(opts);
+    check_matrix(H, "H");
+    check_matrix(S, "S");
+    if (!feat) CHESS_THROW(CHESS_E_ARG, "null feature output");
+    if (!(kT > 0)) CHESS_THROW(CHESS_E_ARG, "kT must be positive");
+    const Pattern *PH = get_pattern(ctx, &H->pat, "H pattern");
+    const Pattern *PS = get_pattern(ctx, &S->pat, "S pattern");
+    const Pattern *PK = get_pattern(ctx, pattern, "kernel pattern");
+    if (PH->nb != PK->nb || PS->nb != PK->nb || PH->b != PK->b || PS->b != PK->b)
+        CHESS_THROW(CHESS_E_ARG, "H, S and the pattern differ in size or block edge");
+    get_embed(ctx, PH, PK, "H in the kernel pattern");
+    get_embed(ctx, PS, PK, "S in the kernel pattern");
+    Frame F;
+    build_frame(ctx, PH, (const double *)H->val, PS, (const double *)S->val, PK, o, F);
+    Features fe;
+    compute_features(ctx, PH, F.Hp.as<double>(), PK, F.s.lo, F.s.hi, n_e, kT, fe);
+    std::memcpy(feat, fe.f, sizeof(fe.f));
+    if (gersh) {
+        gersh[0] = fe.g_lo;
+        gersh[1] = fe.g_hi;
+    }
+}
+
+static void model_load(chess_ctx *ctx, const float *blob, int64_t n) {
+    if (!blob || n != CHESS_MODEL_FLOATS)
+        CHESS_THROW(CHESS_E_ARG, "model blob must hold %d floats (got %lld)", CHESS_MODEL_FLOATS, (long long)n);
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(blob[k])) CHESS_THROW(CHESS_E_ARG, "model blob entry %lld is not finite", (long long)k);
+    for (int k = 0; k < kMlpIn; ++k)
+        if (!(blob[kMlpIn + k] > 0)) CHESS_THROW(CHESS_E_ARG, "model: inverse feature scale %d must be positive", k);
+    Model &M = ctx->model;
+    M.loaded = false;
+    M.blob.assign(blob, blob + n);
+    M.norm.alloc(sizeof(float) * kMlpNorm);
+    M.params.alloc(sizeof(float) * kMlpParams);
+    hipStream_t st = ctx->stream;
+    HIPCHECK(hipMemcpyAsync(M.norm.p, blob, sizeof(float) * kMlpNorm, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(M.params.p, blob + kMlpNorm + 3, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    M.margin_lo = std::max(0.0f, blob[kMlpNorm]);
+    M.margin_hi = std::max(0.0f, blob[kMlpNorm + 1]);
+    M.mu_half = std::max(0.0f, blob[kMlpNorm + 2]);
+    M.loaded = true;
+}
+
 template <typename F>
 static int guarded(chess_ctx *ctx, F &&f) {
     if (!ctx) return CHESS_E_ARG;
@@ -1429,6 +2149,8 @@ static int guarded(chess_ctx *ctx, F &&f) {
 }
 
 }  // namespace chess
+
+using chess::Error;
 
 extern "C" {
 
@@ -1473,6 +2195,7 @@ int chess_destroy(chess_ctx *ctx) {
     if (!ctx) return CHESS_E_ARG;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
     return CHESS_OK;
 }
@@ -1527,6 +2250,66 @@ int chess_chebyshev(chess_ctx *ctx, const chess_matrix *M, double lo, double hi,
 int chess_masked_product(chess_ctx *ctx, const chess_matrix *A, const chess_matrix *B,
                          chess_matrix *C) {
     return chess::guarded(ctx, [&] { chess::masked_product_api(ctx, A, B, C); });
+}
+
+int chess_fermi_operator_batched(chess_ctx *ctx, int32_t nsys, const chess_batch_item *items,
+                                 const chess_opts *opts) {
+    return chess::guarded(ctx, [&] { chess::fermi_batched(ctx, nsys, items, opts); });
+}
+
+int chess_features(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
+                   const chess_pattern *pattern, double n_electrons, double kT, float *feat_out,
+                   double *gersh_out, const chess_opts *opts) {
+    return chess::guarded(ctx, [&] { chess::features_api(ctx, H, S, pattern, n_electrons, kT, feat_out, gersh_out, opts); });
+}
+
+int chess_mlp_forward(chess_ctx *ctx, const float *params, const float *norm, const float *x,
+                      int32_t batch, float *hidden, float *y) {
+    return chess::guarded(ctx, [&] {
+        if (!params || !x || !y || batch < 0) CHESS_THROW(CHESS_E_ARG, "mlp_forward: null pointer or negative batch");
+        HIPCHECK(chess::launch_mlp_forward(params, norm, x, batch, hidden, y, ctx->stream));
+    });
+}
+
+int chess_mlp_grad(chess_ctx *ctx, const float *params, const float *x, const float *hidden,
+                   const float *y, const float *target, int32_t batch, float *work, float *grad,
+                   double *loss) {
+    return chess::guarded(ctx, [&] {
+        if (!params || !x || !hidden || !y || !target || !work || !grad || batch <= 0)
+            CHESS_THROW(CHESS_E_ARG, "mlp_grad: null pointer or empty batch");
+        double *dl = nullptr;
+        if (loss) {
+            if (!ctx->loss_buf.p) ctx->loss_buf.alloc(sizeof(double));
+            dl = ctx->loss_buf.as<double>();
+        }
+        float *dy = work, *dh = work + (size_t)batch * chess::kMlpOut;
+        HIPCHECK(chess::launch_mlp_grad(params, x, hidden, y, target, batch, dy, dh, grad, dl, ctx->stream));
+        if (loss) {
+            HIPCHECK(hipMemcpyAsync(loss, dl, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHECK(hipStreamSynchronize(ctx->stream));
+        }
+    });
+}
+
+int chess_mlp_adam(chess_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n,
+                   float lr, float beta1, float beta2, float eps, int32_t step) {
+    return chess::guarded(ctx, [&] {
+        if (!params || !grad || !m || !v || n < 0 || step < 1)
+            CHESS_THROW(CHESS_E_ARG, "mlp_adam: null pointer, negative size or step < 1");
+        const double c1 = 1.0 - std::pow((double)beta1, step), c2 = 1.0 - std::pow((double)beta2, step);
+        HIPCHECK(chess::launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, (float)c1, (float)c2, ctx->stream));
+    });
+}
+
+int chess_model_load(chess_ctx *ctx, const float *blob, int64_t n) {
+    return chess::guarded(ctx, [&] { chess::model_load(ctx, blob, n); });
+}
+
+int chess_model_save(const chess_ctx *ctx, float *blob, int64_t n) {
+    if (!ctx || !blob || n != CHESS_MODEL_FLOATS) return CHESS_E_ARG;
+    if (!ctx->model.loaded) return CHESS_E_ARG;
+    std::memcpy(blob, ctx->model.blob.data(), sizeof(float) * CHESS_MODEL_FLOATS);
+    return CHESS_OK;
 }
 
 }  // extern "C"

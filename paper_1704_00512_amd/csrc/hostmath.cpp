@@ -3,12 +3,32 @@
 
 #include <algorithm>
 #include <cmath>
+#include <thread>
 
 namespace chess {
 namespace hostmath {
 
 namespace {
 constexpr double kPi = 3.14159265358979323846;
+
+// fn(i) for i in [0, n): large loops are split over up to 16 host threads,
+// each index written by exactly one thread (results do not depend on the
+// split).
+template <typename F>
+void parallel_for(int n, F &&fn) {
+    const int nt = (n >= 512) ? (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency())) : 1;
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(nt);
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            for (int i = t; i < n; i += nt) fn(i);
+        });
+    for (auto &x : th) x.join();
+}
 
 // table[m] = cos(pi m / (2n)), m = 0 .. 4n-1
 std::vector<double> cos_table(int n) {
@@ -32,7 +52,7 @@ std::vector<double> cheb_coeffs_from_samples(const std::vector<double> &fx) {
     if (n == 0) return c;
     const std::vector<double> tab = cos_table(n);
     const int period = 4 * n;
-    for (int j = 0; j < n; ++j) {
+    parallel_for(n, [&](int j) {
         // cos(pi j (2k+1) / (2n)) = tab[j (2k+1) mod 4n]
         int idx = j % period;          // k = 0
         const int stepj = (2 * j) % period;
@@ -43,7 +63,7 @@ std::vector<double> cheb_coeffs_from_samples(const std::vector<double> &fx) {
             if (idx >= period) idx -= period;
         }
         c[j] = 2.0 / n * s;
-    }
+    });
     return c;
 }
 
@@ -69,12 +89,14 @@ double fit_error(const Fn &f, double lo, double hi, int m, int npts) {
     const std::vector<double> c = cheb_coeffs(f, lo, hi, m);
     double sigma, tau;
     scale_shift(lo, hi, &sigma, &tau);
-    double err = 0.0;
-    for (int i = 0; i < npts; ++i) {
+    std::vector<double> e((size_t)npts);
+    parallel_for(npts, [&](int i) {
         const double xs = std::cos(kPi * (double)i / (npts - 1));
         const double x = xs / sigma + tau;
-        err = std::max(err, std::fabs(cheb_eval(c, m, xs) - f(x)));
-    }
+        e[i] = std::fabs(cheb_eval(c, m, xs) - f(x));
+    });
+    double err = 0.0;
+    for (double v : e) err = std::max(err, v);
     return err;
 }
 
@@ -110,7 +132,7 @@ void CountFunction::init(const std::vector<double> &t, double lo_, double hi_, d
     g.assign(n, 0.0);
     const std::vector<double> tab = cos_table(n);
     const int period = 4 * n;
-    for (int m = 0; m < n; ++m) {
+    parallel_for(n, [&](int m) {
         // cos(j theta_m) = cos(pi j (2m+1)/(2n)) = tab[j (2m+1) mod 4n]
         double s = 0.5 * t[0];
         int idx = 0;
@@ -121,7 +143,7 @@ void CountFunction::init(const std::vector<double> &t, double lo_, double hi_, d
             s += t[j] * tab[idx];
         }
         g[m] = s;
-    }
+    });
     cum.assign(n + 1, 0.0);
     for (int m = 0; m < n; ++m) cum[m + 1] = cum[m] + g[m];
 }

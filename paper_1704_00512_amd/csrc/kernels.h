@@ -49,6 +49,11 @@ struct Epilogue {
     double coef[4] = {0, 0, 0, 0};
     void *hist = nullptr;
     double *trace_partial = nullptr;
+    // batches of systems (listed kernel only): when row_sys is set, the
+    // weight of accumulator q for a tile is coef_sys[q][row_sys[first row]]
+    // (tiles never straddle systems) instead of coef[q]
+    const int32_t *row_sys = nullptr;
+    const double *coef_sys[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 struct ProductOperands {
@@ -81,6 +86,7 @@ struct ListedPlanDev {
     //   1: Bt operands read from global memory, same wave count
     //   2: Bt operands from global memory, twice the waves
     //   3: Bt operands from global memory, half the waves
+    //   4, 5 (float32 only): as 1 and 2 with the hit groups software-pipelined
     int variant = 0;
     const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
     const int64_t *j_off = nullptr;      // [ntiles + 1]
@@ -93,6 +99,27 @@ hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
 size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan);
 // number of kernel variants for this dtype / b / plan.cmax (>= 1)
 int listed_product_variants(int dtype, int b, const ListedPlanDev &plan);
+
+// Learned predictor (learned.hip): perceptron sizes, feature histograms.
+constexpr int kMlpIn = 64, kMlpHidden = 128, kMlpOut = 3;
+constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpOut * kMlpHidden + kMlpOut;
+constexpr int kMlpNorm = 2 * kMlpIn + 2 * kMlpOut;
+constexpr int kDiagBins = 24, kRadBins = 16;
+// y [batch][3] = net(x [batch][64]); hid [batch][128] (tanh outputs) if not null
+hipError_t launch_mlp_forward(const float *params, const float *norm, const float *x, int batch,
+                              float *hid, float *y, hipStream_t st);
+// grad = dL/dparams for targets t; dy [batch][3], dh [batch][128] are scratch;
+// loss (device float64, may be null) = L
+hipError_t launch_mlp_grad(const float *params, const float *x, const float *hid, const float *y,
+                           const float *t, int batch, float *dy, float *dh, float *grad,
+                           double *loss, hipStream_t st);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                       float beta1, float beta2, float eps, float c1, float c2, hipStream_t st);
+// hist (kDiagBins + kRadBins uint32, zeroed by the caller); part [parts][6]
+int row_feature_parts(int b, int nb);
+hipError_t launch_row_features(int b, int nb, const int64_t *rp, const int32_t *ci,
+                               const double *val, double c, double w, uint32_t *hist,
+                               double *part, hipStream_t st);
 
 // dtype: 0 = double, 1 = float.  Returns a hipError_t.
 hipError_t launch_masked_product(int dtype, int b, const ProductPlanDev &plan,
@@ -111,6 +138,13 @@ hipError_t launch_scatter_blocks(int dtype_out, int b, int64_t nnzb_in, const in
 hipError_t launch_scale_shift(int b, int64_t nnzb, const int32_t *brow, const int32_t *bcol,
                               const double *in, double *out, double sigma, double tau,
                               hipStream_t st);
+// same with sigma[row_sys[I]] and tau[row_sys[I]] per block row I
+hipError_t launch_scale_shift_rows(int b, int64_t nnzb, const int32_t *brow, const int32_t *bcol,
+                                  const int32_t *row_sys, const double *sigma, const double *tau,
+                                  const double *in, double *out, hipStream_t st);
+// out[k * nseg + s] = sum_{t in [seg[s], seg[s+1])} part[k * ntiles + t], k < nk
+hipError_t launch_segment_sum(int nk, int ntiles, int nseg, const int32_t *seg, const double *part,
+                              double *out, hipStream_t st);
 // out[p] = 0.5 (in[p] + in[tmap[p]]^T)
 hipError_t launch_symmetrize(int b, int64_t nnzb, const int64_t *tmap, const double *in,
                              double *out, hipStream_t st);

@@ -626,6 +626,36 @@ __global__ void k_scale_shift(int b, int64_t nnzb, const int32_t *brow, const in
     }
 }
 
+// Block-diagonal batches: per block row I the system row_sys[I] gives its own
+// sigma and tau.
+__global__ void k_scale_shift_rows(int b, int64_t nnzb, const int32_t *brow, const int32_t *bcol,
+                                   const int32_t *row_sys, const double *sigma, const double *tau,
+                                   const double *in, double *out) {
+    const int64_t bb = (int64_t)b * b;
+    const int64_t n = nnzb * bb;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = x / bb;
+        const int e = (int)(x % bb);
+        const int r = e / b, s = e % b;
+        const int sys = row_sys[brow[p]];
+        const double d = (brow[p] == bcol[p] && r == s) ? tau[sys] : 0.0;
+        out[x] = sigma[sys] * (in[x] - d);
+    }
+}
+
+// out[k * nseg + s] = sum of part[k * ntiles + t] over t in [seg[s], seg[s+1]),
+// in order; grid (nseg, nk).
+__global__ void k_segment_sum(int ntiles, int nseg, const int32_t *seg, const double *part,
+                              double *out) {
+    const int sg = blockIdx.x, k = blockIdx.y;
+    const double *p = part + (int64_t)k * ntiles;
+    double s = 0.0;
+    for (int t = seg[sg] + threadIdx.x; t < seg[sg + 1]; t += blockDim.x) s += p[t];
+    s = block_sum(s);
+    if (threadIdx.x == 0) out[(int64_t)k * nseg + sg] = s;
+}
+
 __global__ void k_symmetrize(int b, int64_t nnzb, const int64_t *tmap, const double *in,
                              double *out) {
     const int64_t bb = (int64_t)b * b;
@@ -863,6 +893,22 @@ hipError_t launch_scatter_blocks(int dtype_out, int b, int64_t nnzb_in, const in
     else
         hipLaunchKernelGGL(k_scatter_blocks<float>, dim3(g), dim3(kWG), 0, st, b, nnzb_in, map,
                            in, (float *)out, transpose);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_shift_rows(int b, int64_t nnzb, const int32_t *brow, const int32_t *bcol,
+                                  const int32_t *row_sys, const double *sigma, const double *tau,
+                                  const double *in, double *out, hipStream_t st) {
+    if (nnzb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_shift_rows, dim3(grid_for(nnzb * b * b)), dim3(kWG), 0, st, b, nnzb,
+                       brow, bcol, row_sys, sigma, tau, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_sum(int nk, int ntiles, int nseg, const int32_t *seg, const double *part,
+                              double *out, hipStream_t st) {
+    if (nk <= 0 || nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_segment_sum, dim3(nseg, nk), dim3(kWG), 0, st, ntiles, nseg, seg, part, out);
     return hipGetLastError();
 }
 

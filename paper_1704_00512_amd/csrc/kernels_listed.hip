@@ -97,7 +97,7 @@ __device__ inline void decode(const void *ent, int idx, int &pa, int &sl) {
     }
 }
 
-template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD>
+template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE>
 __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductOperands ops,
                                                     Epilogue ep) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -114,6 +114,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     static_assert(!MFMA || (B == 4 && CMAX == 4 && sizeof(T) == 4), "MFMA path: float, b = 4");
     static_assert(!MF64 || (B == 4 && CMAX == 4 && sizeof(T) == 8), "MFMA64 path: double, b = 4");
     static_assert(!BD || MFMA || MF64, "direct Bt operands: MFMA paths only");
+    static_assert(!PIPE || (MFMA && BD), "pipelined hit groups: float32 MFMA path with direct operands");
 
     const int ntiles = plan.ntiles;
     const int nt8 = (ntiles + 7) & ~7;
@@ -182,6 +183,13 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
 
     const int64_t j0 = plan.j_off[tile];
     const int nj = (int)(plan.j_off[tile + 1] - j0);
+    // accumulator weights of this tile (one system per tile in batches)
+    double wq[4];
+    {
+        const int sys = ep.row_sys ? ep.row_sys[row0] : 0;
+#pragma unroll
+        for (int qa = 0; qa < 4; ++qa) wq[qa] = (ep.row_sys && ep.coef_sys[qa]) ? ep.coef_sys[qa][sys] : ep.coef[qa];
+    }
     const int4 *recs = reinterpret_cast<const int4 *>(plan.j_rec);
     const T *BtV = reinterpret_cast<const T *>(ops.bt_val);
     const T *Prev = reinterpret_cast<const T *>(ep.prev);
@@ -354,6 +362,43 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
                     bp = ok ? b_base + (sl << 6) : zp;
             };
             int it = 0;
+            if constexpr (PIPE) {
+                // groups of four hits per slot, software-pipelined: the
+                // operands of group g + 1 are loaded while the MFMAs of group g
+                // run (two register sets in turn); the remainder below
+                auto load = [&](int g, f32x4 *a, f32x4 *bq) __attribute__((always_inline)) {
+                    lds_u8 *ap[4];
+                    b_u8 *bp[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) addr(grp + 4 * (4 * g + u), ap[u], bp[u]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a[u] = *(lds_f4 *)ap[u];
+                        bq[u] = *(b_f4 *)bp[u];
+                    }
+                };
+                auto mma = [&](const f32x4 *a, const f32x4 *bq) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][0], bq[u][0], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][1], bq[u][1], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][2], bq[u][2], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][3], bq[u][3], acc, 0, 0, 0);
+                    }
+                };
+                const int groups = iters >> 2;
+                f32x4 a0[4], b0[4], a1[4], b1[4];
+                if (groups > 0) load(0, a0, b0);
+                int g = 0;
+                for (; g + 2 <= groups; g += 2) {
+                    load(g + 1, a1, b1);
+                    mma(a0, b0);
+                    if (g + 2 < groups) load(g + 2, a0, b0);
+                    mma(a1, b1);
+                }
+                if (g < groups) mma(a0, b0);
+                it = groups * 4;
+            }
             // four hits per slot at a time: all LDS reads issued before the MFMAs
             for (; it + 4 <= iters; it += 4) {
                 lds_u8 *ap[4];
@@ -508,7 +553,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             const double od = (double)o;
 #pragma unroll
             for (int qa = 0; qa < 4; ++qa)
-                if (qa < ep.nacc) ep.acc[qa][C.off[q]] = C.acc[q][qa] + ep.coef[qa] * od;
+                if (qa < ep.nacc) ep.acc[qa][C.off[q]] = C.acc[q][qa] + wq[qa] * od;
             if (ep.hist) reinterpret_cast<T *>(ep.hist)[C.off[q]] = o;
             if (row0 + ei[q] == jc && er[q] == es[q]) tr += od;
         }
@@ -538,10 +583,10 @@ struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
     static constexpr int MODE = (B == 4 && CMAX == 4) ? (std::is_same<T, float>::value ? 1 : 2) : 0;
     static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int COUNT = MODE == 0 ? 1 : 4;
+    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 6 : 4);
 };
 
-template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD>
+template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE = false>
 hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
                     hipStream_t st, size_t *lds_out) {
     const size_t lds = listed_lds<T, B, NW, EW, BD>(plan).total;
@@ -550,7 +595,7 @@ hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const
         return hipSuccess;
     }
     if (plan.ntiles == 0) return hipSuccess;
-    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW, BD>;
+    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE>;
     static int raised_device = -1;
     static size_t raised_to = 0;
     int dev = 0;
@@ -562,7 +607,7 @@ hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const
         raised_to = lds;
     }
     const int nt8 = (plan.ntiles + 7) & ~7;
-    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW, BD>), dim3(nt8), dim3(64 * NW), lds, st,
+    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE>), dim3(nt8), dim3(64 * NW), lds, st,
                        plan, ops, ep);
     return hipGetLastError();
 }
@@ -582,6 +627,12 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
             case 1: return launch_v<T, B, CMAX, NW, MODE, EW, true>(plan, ops, ep, st, lds_out);
             case 2: return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true>(plan, ops, ep, st, lds_out);
             case 3: return launch_v<T, B, CMAX, NW / 2, MODE, EW, true>(plan, ops, ep, st, lds_out);
+            case 4:
+                if constexpr (MODE == 1) return launch_v<T, B, CMAX, NW, MODE, EW, true, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 5:
+                if constexpr (MODE == 1) return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
     }

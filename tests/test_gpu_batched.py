@@ -1,0 +1,105 @@
+"""Batches of independent systems (chess_fermi_operator_batched) against the
+oracle, system by system, and against the same batch run without graph
+capture."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import pipeline as opl
+from paper_1704_00512_amd import BlockPattern, ChessError, chess_fermi_operator_batched
+from workloads import generator as g
+
+pytestmark = pytest.mark.gpu
+
+# mixed sizes and both block edges; several tiles per system
+SPECS = [(37, 4, 4.6, 6.2, 31, 0.02), (21, 9, 4.6, 6.2, 32, 0.01), (58, 4, 4.6, 6.2, 33, 0.015),
+         (15, 9, 4.6, 6.2, 34, 0.02), (9, 4, 4.6, 6.2, 35, 0.03)]
+_sys = {}
+
+
+def systems():
+    if not _sys:
+        for sp in SPECS:
+            print(f"[batched] system {sp}", flush=True)
+            _sys[sp] = g.make_system(*sp[:4], seed=sp[4], kT=sp[5])
+    return [_sys[sp] for sp in SPECS]
+
+
+def dv(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def batch_args(ss, mu_shift=(-0.05, 0.0, 0.04)):
+    out = []
+    for s in ss:
+        ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx)
+        pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx)
+        out.append(dict(H=dv(s.H), pat_h=ph, S=dv(s.S), pat_s=ph, pattern=pk,
+                        n_electrons=s.n_electrons, kT=s.kT,
+                        mu_trial=tuple(-0.9 + d for d in mu_shift)))
+    return out
+
+
+def bm(p, v=None):
+    return opl.BlockMat(p.nb, p.b, p.row_ptr, p.col_idx, v)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_batched_matches_oracle_per_system(gpu_ctx, precision, tol):
+    ss = systems()
+    args = batch_args(ss)
+    res = chess_fermi_operator_batched(gpu_ctx, args, precision=precision, bounds_mode="lanczos")
+    for s, a, r in zip(ss, args, res):
+        inf = r["info"]
+        sb, hb = (inf["s_lo"], inf["s_hi"]), (inf["lo"], inf["hi"])
+        H, S, P = bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k)
+        X, xi = opl.matrix_power(S, -0.5, P, bounds=sb, n_pl=inf["n_pl_s"])
+        Si, _ = opl.matrix_power(S, -1.0, P, bounds=sb, n_pl=inf["n_pl_s"])
+        assert np.max(np.abs(r["Sinvhalf"].cpu().numpy() - X)) < tol
+        assert np.max(np.abs(r["Sinv"].cpu().numpy() - Si)) < tol * 10
+        for q in range(3):
+            Ko, _ = opl.fermi_operator(H, S, P, s.n_electrons, s.kT, s_bounds_=sb,
+                                       n_pl_s=inf["n_pl_s"], h_bounds=hb, n_pl=inf["n_pl"],
+                                       mu=a["mu_trial"][q])
+            assert np.max(np.abs(r["K"][q].cpu().numpy() - Ko)) < tol, (s.n, q)
+        # mu from the moments
+        _, oi = opl.fermi_operator(H, S, P, s.n_electrons, s.kT, s_bounds_=sb,
+                                   n_pl_s=inf["n_pl_s"], h_bounds=hb, n_pl=inf["n_pl"])
+        assert abs(inf["mu"] - oi["mu"]) < (1e-8 if precision == "f64" else 1e-5)
+        assert r["ne_trial"][0] < r["ne_trial"][1] < r["ne_trial"][2]
+
+
+def test_graph_and_eager_launches_agree_bitwise(gpu_ctx, monkeypatch):
+    ss = systems()
+    r_graph = chess_fermi_operator_batched(gpu_ctx, batch_args(ss), precision="f32",
+                                           bounds_mode="lanczos")
+    monkeypatch.setenv("CHESS_BATCH_GRAPH", "0")
+    r_eager = chess_fermi_operator_batched(gpu_ctx, batch_args(ss), precision="f32",
+                                           bounds_mode="lanczos")
+    for a, b in zip(r_graph, r_eager):
+        for q in range(3):
+            assert torch.equal(a["K"][q], b["K"][q])
+        assert torch.equal(a["Sinvhalf"], b["Sinvhalf"])
+
+
+def test_single_system_batch_and_short_chain(gpu_ctx):
+    s = systems()[0]
+    args = batch_args([s])
+    res = chess_fermi_operator_batched(gpu_ctx, args, precision="f64", bounds_mode="gershgorin",
+                                       n_pl=3, n_pl_s=3)
+    inf = res[0]["info"]
+    H, S, P = bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k)
+    Ko, _ = opl.fermi_operator(H, S, P, s.n_electrons, s.kT, s_bounds_=(inf["s_lo"], inf["s_hi"]),
+                               n_pl_s=3, h_bounds=(inf["lo"], inf["hi"]), n_pl=3,
+                               mu=args[0]["mu_trial"][1])
+    assert np.max(np.abs(res[0]["K"][1].cpu().numpy() - Ko)) < 1e-10
+
+
+def test_batched_errors(gpu_ctx):
+    ss = systems()[:2]
+    args = batch_args(ss)
+    args[1]["mu_trial"] = (float("nan"),) * 3  # no predictor in this context
+    with pytest.raises(ChessError):
+        chess_fermi_operator_batched(gpu_ctx, args, bounds_mode="lanczos")
+    with pytest.raises(ChessError):
+        chess_fermi_operator_batched(gpu_ctx, [], bounds_mode="lanczos")

@@ -311,6 +311,41 @@ CONFIGS = {
 }
 
 
+# Systems of the learned-predictor data set: physical knobs drawn per seed
+# (train seeds 40000 + i, held-out seeds 50000 + i).  Atom counts are
+# log-uniform in [n_min, n_max]; b is 4 or 9 with probability 1/2; onsite
+# energies are spread +-0.2 Ha around a mean drawn from [-0.8, -0.2]; the
+# hopping scale is drawn from [0.2, 0.4]; kT is log-uniform in [0.002, 0.02];
+# the filling N_e / n is drawn from [0.25, 0.75]; cutoffs of the 9000-row
+# workload (4.57 / 5.99 bohr).
+PREDICTOR_TRAIN_SEED0, PREDICTOR_TEST_SEED0 = 40000, 50000
+
+
+def predictor_system(seed: int, n_min: int = 40, n_max: int = 300) -> System:
+    rng = np.random.default_rng(seed)
+    n_atoms = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
+    b = 4 if rng.uniform() < 0.5 else 9
+    m = rng.uniform(-0.8, -0.2)
+    hop = rng.uniform(0.2, 0.4)
+    kT = float(np.exp(rng.uniform(np.log(0.002), np.log(0.02))))
+    filling = rng.uniform(0.25, 0.75)
+    return make_system(n_atoms, b, 4.57, 5.99, seed=seed, kT=kT, filling=filling,
+                       onsite=(m - 0.2, m + 0.2), hop=hop)
+
+
+# The batched workload: 48 systems, atom counts log-uniform in [200, 4000],
+# b = 4 or 9 with probability 1/2, cutoffs of the 9000-row workload, kT 0.005,
+# half filling; system i uses seed 3000 + i.
+BATCH_SEED0, BATCH_SYSTEMS = 3000, 48
+
+
+def batched_system(i: int, n_min: int = 200, n_max: int = 4000) -> System:
+    rng = np.random.default_rng(BATCH_SEED0 + i)
+    n_atoms = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
+    b = 4 if rng.uniform() < 0.5 else 9
+    return make_system(n_atoms, b, 4.57, 5.99, seed=BATCH_SEED0 + i, kT=0.005)
+
+
 def make_config(name: str, **over) -> System:
     kw = dict(CONFIGS[name])
     kw.update(over)
