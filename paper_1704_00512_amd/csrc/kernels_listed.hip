@@ -377,26 +377,31 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
                         bq[u] = *(b_f4 *)bp[u];
                     }
                 };
-                auto mma = [&](const f32x4 *a, const f32x4 *bq) __attribute__((always_inline)) {
+                auto mma = [&](const f32x4 *a, const f32x4 *bq, f32x4 &c) __attribute__((always_inline)) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][0], bq[u][0], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][1], bq[u][1], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][2], bq[u][2], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][3], bq[u][3], acc, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][0], bq[u][0], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][1], bq[u][1], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][2], bq[u][2], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][3], bq[u][3], c, 0, 0, 0);
                     }
                 };
+                // Loads run one group ahead unconditionally (a group past the
+                // list reads the zero block and slot 0: valid addresses, zero
+                // products), so the wait before each group's MFMAs only covers
+                // that group's loads; two accumulators keep consecutive MFMAs
+                // independent.
                 const int groups = iters >> 2;
                 f32x4 a0[4], b0[4], a1[4], b1[4];
-                if (groups > 0) load(0, a0, b0);
-                int g = 0;
-                for (; g + 2 <= groups; g += 2) {
+                f32x4 acc1 = {0.f, 0.f, 0.f, 0.f};
+                load(0, a0, b0);
+                for (int g = 0; g < groups; g += 2) {
                     load(g + 1, a1, b1);
-                    mma(a0, b0);
-                    if (g + 2 < groups) load(g + 2, a0, b0);
-                    mma(a1, b1);
+                    mma(a0, b0, acc);
+                    load(g + 2, a0, b0);
+                    if (g + 1 < groups) mma(a1, b1, acc1);
                 }
-                if (g < groups) mma(a0, b0);
+                acc += acc1;
                 it = groups * 4;
             }
             // four hits per slot at a time: all LDS reads issued before the MFMAs
