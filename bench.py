@@ -195,6 +195,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
+    ap.add_argument("--chain-only", type=int, default=0, metavar="N_PL",
+                    help="only run one N_PL-term chain (one accumulator) on the workload's H, "
+                         "for counter collection")
+    ap.add_argument("--precision", default="f32", help="--chain-only: f32 or f64")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="--chain-only: force this chain-kernel variant (CHESS_LISTED_VARIANT)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the multi-GPU column-slab sharding is a design "
@@ -206,6 +212,26 @@ def main():
 
     if args.workload == "batched48":
         bench_batched(args)
+        return
+
+    if args.chain_only:
+        from paper_1704_00512_amd import BlockPattern, Context, chess_chebyshev
+        from workloads.generator import make_config
+        if args.variant >= 0:
+            os.environ["CHESS_LISTED_VARIANT"] = str(args.variant)
+        sysm = make_config(args.workload)
+        dev = torch.device("cuda:0")
+        ph = BlockPattern.from_host(sysm.b, sysm.pat_h.row_ptr, sysm.pat_h.col_idx, dev)
+        pk = BlockPattern.from_host(sysm.b, sysm.pat_k.row_ptr, sysm.pat_k.col_idx, dev)
+        ctx = Context(0)
+        n = args.chain_only
+        t0 = time.perf_counter()
+        _, mom = chess_chebyshev(ctx, torch.tensor(sysm.H, device=dev), ph, -3.0, 0.5, pk, n,
+                                 np.ones((1, n)) * 1e-3, precision=args.precision)
+        torch.cuda.synchronize()
+        log(f"chain of {n} terms ({args.precision}, variant {args.variant}): "
+            f"{(time.perf_counter() - t0) * 1e3:.0f} ms, t_1 = {mom[1]:.6f}")
+        ctx.close()
         return
 
     if args.calibrate_copy:

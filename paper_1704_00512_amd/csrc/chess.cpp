@@ -737,8 +737,8 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
     if (const char *env = std::getenv("CHESS_LISTED_VARIANT")) {
         char *end = nullptr;
         const long v = std::strtol(env, &end, 10);
-        if (end == env || v < 0 || v >= nvar)
-            CHESS_THROW(CHESS_E_ARG, "CHESS_LISTED_VARIANT=%s: expected 0..%d", env, nvar - 1);
+        if (end == env || !listed_product_variant_ok(dtype, b, lp->dev, (int)v))
+            CHESS_THROW(CHESS_E_ARG, "CHESS_LISTED_VARIANT=%s: no such kernel variant here (ids 0..%d)", env, nvar - 1);
         lp->dev.variant = (int)v;
         if (listed_product_lds_bytes(dtype, b, lp->dev) > 160 * 1024)
             CHESS_THROW(CHESS_E_UNSUPPORTED, "kernel variant %ld needs more than 160 KB of LDS", v);
@@ -770,7 +770,7 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
     for (int v = 0; v < nvar; ++v) {
         ListedPlanDev d = lp->dev;
         d.variant = v;
-        if (listed_product_lds_bytes(dtype, b, d) > 160 * 1024) continue;
+        if (!listed_product_variant_ok(dtype, b, d, v) || listed_product_lds_bytes(dtype, b, d) > 160 * 1024) continue;
         HIPCHECK(launch_listed_product(dtype, b, d, ops, ep, st));
         tm.start();
         for (int r = 0; r < 3; ++r) HIPCHECK(launch_listed_product(dtype, b, d, ops, ep, st));

@@ -87,6 +87,7 @@ struct ListedPlanDev {
     //   2: Bt operands from global memory, twice the waves
     //   3: Bt operands from global memory, half the waves
     //   4, 5 (float32 only): as 1 and 2 with the hit groups software-pipelined
+    //   6, 7: as 1 and 2 with non-temporal hints on the streamed data
     int variant = 0;
     const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
     const int64_t *j_off = nullptr;      // [ntiles + 1]
@@ -97,8 +98,10 @@ struct ListedPlanDev {
 hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
                                  const ProductOperands &ops, const Epilogue &ep, hipStream_t st);
 size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan);
-// number of kernel variants for this dtype / b / plan.cmax (>= 1)
+// number of kernel variant ids for this dtype / b / plan.cmax (>= 1), and
+// whether id v exists
 int listed_product_variants(int dtype, int b, const ListedPlanDev &plan);
+bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int v);
 
 // Learned predictor (learned.hip): perceptron sizes, feature histograms.
 constexpr int kMlpIn = 64, kMlpHidden = 128, kMlpOut = 3;

@@ -35,6 +35,26 @@ namespace chess {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Streamed data (A tile rows, records, hit lists, T_{k-1}, accumulators,
+// outputs) is touched once per launch; with NTH it carries the non-temporal
+// hint so that L2 keeps the rows of Bt, which many tiles re-read.
+template <bool NTH, typename V>
+__device__ inline V ld_stream(const V *p) {
+    if constexpr (NTH)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NTH, typename V>
+__device__ inline void st_stream(V *p, V v) {
+    if constexpr (NTH)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -97,7 +117,7 @@ __device__ inline void decode(const void *ent, int idx, int &pa, int &sl) {
     }
 }
 
-template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE>
+template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE, bool NTH>
 __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductOperands ops,
                                                     Epilogue ep) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -133,11 +153,11 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     {
         const int nab = (int)(ops.a_rp[row0 + c] - ab0);
         const T *Ag = reinterpret_cast<const T *>(ops.a_val) + ab0 * BB;
-        if (V16OK) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(Ag);
-            uint4 *dst = reinterpret_cast<uint4 *>(As);
-            const int n16 = nab * V16;
-            for (int x = threadIdx.x; x < n16; x += NT) dst[x] = src[x];
+        if ((BB * sizeof(T)) % 16 == 0) {
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(Ag);
+            u32x4 *dst = reinterpret_cast<u32x4 *>(As);
+            const int n16 = nab * (int)((BB * sizeof(T)) / 16);
+            for (int x = threadIdx.x; x < n16; x += NT) dst[x] = ld_stream<NTH>(src + x);
         } else {
             for (int x = threadIdx.x; x < nab * BB; x += NT) As[x] = Ag[x];
         }
@@ -205,8 +225,10 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
 #define LREC(JJ, RA, RB)                                                              \
     do {                                                                              \
         if ((JJ) < nj) {                                                              \
-            RA = recs[2 * (j0 + (JJ))];                                               \
-            RB = recs[2 * (j0 + (JJ)) + 1];                                           \
+            const i32x4 *r_ = reinterpret_cast<const i32x4 *>(recs) + 2 * (j0 + (JJ)); \
+            const i32x4 a_ = ld_stream<NTH>(r_), b_ = ld_stream<NTH>(r_ + 1);          \
+            RA = make_int4(a_.x, a_.y, a_.z, a_.w);                                   \
+            RB = make_int4(b_.x, b_.y, b_.z, b_.w);                                   \
         } else {                                                                      \
             RA = make_int4(-1, 0, 0, 0);                                              \
         }                                                                             \
@@ -228,7 +250,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             const int nwv_ = ((tot_ * 2 * EW + 3) / 4 + 63) >> 6;                     \
             const uint32_t *es_ = E32 + ((int64_t)(RA).w * 2 * EW) / 4 + lane;        \
             _Pragma("unroll") for (int v_ = 0; v_ < kEntWords; ++v_)                  \
-                EWD[v_] = (v_ < nwv_) ? es_[v_ * 64] : 0u;                            \
+                EWD[v_] = (v_ < nwv_) ? ld_stream<NTH>(es_ + v_ * 64) : 0u;           \
         }                                                                             \
     } while (0)
 
@@ -247,9 +269,9 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             VAL[q_] = (RA).x >= 0 && ei[q_] < c && op_ != 0xFFFFu;                    \
             /* lanes without an output read element 0 and drop the value */          \
             OFF[q_] = VAL[q_] ? (cb_ + op_) * BB + er[q_] * B + es[q_] : 0;           \
-            if (Prev) PRV[q_] = Prev[OFF[q_]];                                        \
+            if (Prev) PRV[q_] = ld_stream<NTH>(Prev + OFF[q_]);                       \
             _Pragma("unroll") for (int qa_ = 0; qa_ < 4; ++qa_)                       \
-                if (qa_ < ep.nacc) ACCV[q_][qa_] = ep.acc[qa_][OFF[q_]];             \
+                if (qa_ < ep.nacc) ACCV[q_][qa_] = ld_stream<NTH>(ep.acc[qa_] + OFF[q_]); \
         }                                                                             \
     } while (0)
 
@@ -554,12 +576,12 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             if (!C.valid[q]) continue;
             T o = (T)ep.alpha * y[q];
             if (Prev) o = fma((T)ep.beta, C.prev[q], o);
-            reinterpret_cast<T *>(ops.c_out)[C.off[q]] = o;
+            st_stream<NTH>(reinterpret_cast<T *>(ops.c_out) + C.off[q], o);
             const double od = (double)o;
 #pragma unroll
             for (int qa = 0; qa < 4; ++qa)
-                if (qa < ep.nacc) ep.acc[qa][C.off[q]] = C.acc[q][qa] + wq[qa] * od;
-            if (ep.hist) reinterpret_cast<T *>(ep.hist)[C.off[q]] = o;
+                if (qa < ep.nacc) st_stream<NTH>(ep.acc[qa] + C.off[q], C.acc[q][qa] + wq[qa] * od);
+            if (ep.hist) st_stream<NTH>(reinterpret_cast<T *>(ep.hist) + C.off[q], o);
             if (row0 + ei[q] == jc && er[q] == es[q]) tr += od;
         }
         wave_sync_lds();
@@ -588,10 +610,13 @@ struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
     static constexpr int MODE = (B == 4 && CMAX == 4) ? (std::is_same<T, float>::value ? 1 : 2) : 0;
     static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 6 : 4);
+    static constexpr int COUNT = MODE == 0 ? 1 : 8;
+    // variants 4 and 5 (pipelined hit groups) exist for float32 only
+    static bool ok(int v) { return v >= 0 && v < COUNT && (MODE == 1 || (v != 4 && v != 5)); }
 };
 
-template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE = false>
+template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE = false,
+          bool NTH = false>
 hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
                     hipStream_t st, size_t *lds_out) {
     const size_t lds = listed_lds<T, B, NW, EW, BD>(plan).total;
@@ -600,7 +625,7 @@ hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const
         return hipSuccess;
     }
     if (plan.ntiles == 0) return hipSuccess;
-    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE>;
+    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH>;
     static int raised_device = -1;
     static size_t raised_to = 0;
     int dev = 0;
@@ -612,7 +637,7 @@ hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const
         raised_to = lds;
     }
     const int nt8 = (plan.ntiles + 7) & ~7;
-    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE>), dim3(nt8), dim3(64 * NW), lds, st,
+    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH>), dim3(nt8), dim3(64 * NW), lds, st,
                        plan, ops, ep);
     return hipGetLastError();
 }
@@ -638,6 +663,8 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
             case 5:
                 if constexpr (MODE == 1) return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true, true>(plan, ops, ep, st, lds_out);
                 return hipErrorInvalidValue;
+            case 6: return launch_v<T, B, CMAX, NW, MODE, EW, true, false, true>(plan, ops, ep, st, lds_out);
+            case 7: return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true, false, true>(plan, ops, ep, st, lds_out);
             default: return hipErrorInvalidValue;
         }
     }
@@ -681,6 +708,11 @@ hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
 int listed_product_variants(int dtype, int b, const ListedPlanDev &plan) {
     if (b != 4 || plan.cmax != 4) return 1;
     return dtype == 0 ? LVariant<double, 4, 4>::COUNT : LVariant<float, 4, 4>::COUNT;
+}
+
+bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int v) {
+    if (b != 4 || plan.cmax != 4) return v == 0;
+    return dtype == 0 ? LVariant<double, 4, 4>::ok(v) : LVariant<float, 4, 4>::ok(v);
 }
 
 size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan) {
