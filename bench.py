@@ -129,12 +129,15 @@ def bench_batched(args):
                                       chess_fermi_operator_batched)
     from workloads.generator import BATCH_SYSTEMS, batched_system
     t0 = time.time()
-    with mp.get_context("spawn").Pool(12) as pool:
+    log("generating the batch")
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"  # many single-threaded generator processes
+    with mp.get_context("spawn").Pool(14) as pool:
         ss = []
-        for k, s in enumerate(pool.imap(batched_system, range(BATCH_SYSTEMS))):
+        for k, s in enumerate(pool.imap_unordered(batched_system, range(BATCH_SYSTEMS))):
             ss.append(s)
-            if (k + 1) % 8 == 0:
-                log(f"generated {k + 1}/{BATCH_SYSTEMS} systems ({time.time() - t0:.0f} s)")
+            log(f"generated {k + 1}/{BATCH_SYSTEMS}: {s.n} rows, b={s.b} ({time.time() - t0:.0f} s)")
+    ss.sort(key=lambda s: s.meta["seed"])
     dev = torch.device("cuda:0")
     mu_tr = (-0.55, -0.5, -0.45)
     args_b = []
@@ -207,6 +210,7 @@ def main():
               "(see DESIGN.md), not part of this build", file=sys.stderr)
         sys.exit(2)
 
+    log("importing torch")
     import numpy as np
     import torch
 
@@ -309,7 +313,8 @@ def main():
     else:
         roof = dict(bound="alu", achieved=round(tflops, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(tflops / FP32_PEAK_TFLOPS, 4))
-    roof.update(traffic=traffic, kernel="k_listed<float,4,4,...> (chain product)",
+    roof.update(traffic=traffic, kernel=f"k_listed<float,4,4,...> (chain product), variant "
+                                        f"{info['kernel_variant']} chosen by timing",
                 avg_launch_ms=round(avg_launch_ms, 4),
                 algorithmic_bytes_per_call=int(bytes_call), launches_per_call=launches_call,
                 flops_per_launch=flops_launch, achieved_gbs=round(gbs, 1),

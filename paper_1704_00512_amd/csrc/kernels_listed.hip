@@ -514,6 +514,29 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
                     bp = ok ? b_base + (sl << 7) : zp;
             };
             int h = 0;
+            // with operands from global memory, 8 hits per wait (one MFMA
+            // each) and two accumulators in turn
+            if constexpr (BD) {
+                double acc2 = 0.0;
+                for (; h + 8 <= nmax; h += 8) {
+                    lds_u8 *ap[8];
+                    b_u8 *bp[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) addr(h + u, ap[u], bp[u]);
+                    double a[8], bb[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        a[u] = *(lds_d *)ap[u];
+                        bb[u] = *(b_d *)bp[u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; u += 2) {
+                        acc = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u], bb[u], acc, 0, 0, 0);
+                        acc2 = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u + 1], bb[u + 1], acc2, 0, 0, 0);
+                    }
+                }
+                acc += acc2;
+            }
             for (; h + 4 <= nmax; h += 4) {
                 lds_u8 *ap[4];
                 b_u8 *bp[4];
