@@ -1,52 +1,99 @@
-"""Parity at the benchmark's full size (the 80 000-row workload, its kernel
-pattern of 4 006 768 blocks) on sampled outputs: block columns of the chain's
-sums from the library (float32 chain, kernel variant chosen by timing as in
-the benchmark) against the oracle's column recursion in float64."""
+"""Parity at full workload sizes on sampled outputs: block columns of chain
+sums and of S^-1/2 from the library against the oracle's column recursion in
+float64 (columns of a truncated chain are independent, so the oracle computes
+single columns at any size).
+
+  large80k: 80 000 rows, b = 4, kernel pattern 4 006 768 blocks - the float32
+            chain in the benchmark's launch configuration (kernel variant
+            chosen by timing);
+  prec9000: 9 000 rows, b = 9 - S^-1/2 in float64 and float32 (the precision
+            study), and the chain on H.
+"""
 import numpy as np
 import pytest
 import torch
 
+from oracle import chebyshev as cb
 from oracle import columns as oc
 from oracle import pipeline as opl
-from paper_1704_00512_amd import BlockPattern, chess_chebyshev
+from paper_1704_00512_amd import BlockPattern, chess_chebyshev, chess_matrix_power
 from workloads import generator as g
 
 pytestmark = pytest.mark.gpu
 
+_sys = {}
 
-def test_large80k_chain_sampled_columns(gpu_ctx):
-    print("[fullsize] generating large80k", flush=True)
-    s = g.make_config("large80k")
-    dev = torch.device("cuda")
-    ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx, dev)
-    pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx, dev)
-    lo, hi = -3.0, 0.5  # contains the spectrum of H (Gershgorin-free margin checked below)
-    n_pl = 80
-    rng = np.random.default_rng(11)
-    coefs = rng.standard_normal((2, n_pl)) / np.arange(1, n_pl + 1)
-    print("[fullsize] chain on the GPU", flush=True)
-    accs, mom = chess_chebyshev(gpu_ctx, torch.tensor(s.H, device=dev), ph, lo, hi, pk, n_pl,
-                                coefs, precision="f32")
-    got = [a.cpu().numpy() for a in accs]
-    # every |Tr T_k| <= n holds only if the spectrum is inside [lo, hi]
-    assert np.all(np.abs(mom) <= 1.0001 * s.n)
-    print("[fullsize] oracle columns", flush=True)
-    H = opl.BlockMat(s.pat_h.nb, s.b, s.pat_h.row_ptr, s.pat_h.col_idx, s.H)
-    Mt = opl.scaled(H.csr(), lo, hi)
+
+def workload(name):
+    if name not in _sys:
+        print(f"[fullsize] generating {name}", flush=True)
+        _sys[name] = g.make_config(name)
+    return _sys[name]
+
+
+def max_column_error(s, blocks, Mt, n_pl, coefs, cols):
+    """max |library - oracle| over the scalar columns `cols` of each coefficient
+    set; blocks[q] are the library's [nnzb, b, b] values on the kernel pattern."""
     K = opl.BlockMat(s.pat_k.nb, s.b, s.pat_k.row_ptr, s.pat_k.col_idx).pattern_csr()
     b = s.b
-    cols = np.sort(rng.choice(s.n, size=12, replace=False))
     worst = 0.0
     for c in cols:
         S, ref = oc.chain_column(Mt, K, int(c), n_pl, coefs)
         J, sc = int(c) // b, int(c) % b
-        # blocks (I, J) of column J, I ascending = row J of the symmetric pattern
         I = s.pat_k.col_idx[s.pat_k.row_ptr[J]:s.pat_k.row_ptr[J + 1]].astype(np.int64)
         pos = g.positions_in_pattern(s.pat_k, I, np.full(I.size, J))
         assert np.all(pos >= 0)
         assert np.array_equal(S, (I[:, None] * b + np.arange(b)[None, :]).ravel())
-        for q in range(2):
-            col = got[q][pos][:, :, sc].ravel()  # rows I*b + r, column J*b + sc
+        for q, blk in enumerate(blocks):
+            col = blk[pos][:, :, sc].ravel()  # rows I*b + r of column J*b + sc
             worst = max(worst, float(np.max(np.abs(col - ref[q]))))
-    print(f"[fullsize] max |GPU - oracle| over {cols.size} columns: {worst:.3e}", flush=True)
-    assert worst < 1e-5
+    return worst
+
+
+def chain_check(gpu_ctx, name, precision, tol, n_pl, lo, hi, ncols):
+    s = workload(name)
+    dev = torch.device("cuda")
+    ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx, dev)
+    pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx, dev)
+    rng = np.random.default_rng(11)
+    coefs = rng.standard_normal((2, n_pl)) / np.arange(1, n_pl + 1)
+    print(f"[fullsize] {name} {precision} chain on the GPU", flush=True)
+    accs, mom = chess_chebyshev(gpu_ctx, torch.tensor(s.H, device=dev), ph, lo, hi, pk, n_pl,
+                                coefs, precision=precision)
+    # |Tr T_k| <= n holds when the spectrum of H is inside [lo, hi]
+    assert np.all(np.abs(mom) <= 1.0001 * s.n)
+    H = opl.BlockMat(s.pat_h.nb, s.b, s.pat_h.row_ptr, s.pat_h.col_idx, s.H)
+    cols = np.sort(rng.choice(s.n, size=ncols, replace=False))
+    worst = max_column_error(s, [a.cpu().numpy() for a in accs], opl.scaled(H.csr(), lo, hi),
+                             n_pl, coefs, cols)
+    print(f"[fullsize] {name} {precision} chain: max |GPU - oracle| over {ncols} columns "
+          f"= {worst:.3e}", flush=True)
+    assert worst < tol
+
+
+def test_large80k_chain_sampled_columns(gpu_ctx):
+    chain_check(gpu_ctx, "large80k", "f32", 1e-5, 80, -3.0, 0.5, 12)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_prec9000_chain_sampled_columns(gpu_ctx, precision, tol):
+    chain_check(gpu_ctx, "prec9000", precision, tol, 70, -3.0, 0.5, 16)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_prec9000_inverse_sqrt_sampled_columns(gpu_ctx, precision, tol):
+    s = workload("prec9000")
+    dev = torch.device("cuda")
+    ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx, dev)
+    pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx, dev)
+    print(f"[fullsize] prec9000 {precision} S^-1/2 on the GPU", flush=True)
+    R, info = chess_matrix_power(gpu_ctx, torch.tensor(s.S, device=dev), ph, -0.5, pk,
+                                 precision=precision)
+    lo, hi, n_pl = info["lo"], info["hi"], info["n_pl"]
+    coefs = cb.cheb_coeffs(cb.power_fn(-0.5), lo, hi, n_pl)[None, :]
+    S = opl.BlockMat(s.pat_h.nb, s.b, s.pat_h.row_ptr, s.pat_h.col_idx, s.S)
+    cols = np.sort(np.random.default_rng(12).choice(s.n, size=16, replace=False))
+    worst = max_column_error(s, [R.cpu().numpy()], opl.scaled(S.csr(), lo, hi), n_pl, coefs, cols)
+    print(f"[fullsize] prec9000 {precision} S^-1/2 (bounds [{lo:.4f}, {hi:.4f}], n_pl {n_pl}): "
+          f"max |GPU - oracle| over 16 columns = {worst:.3e}", flush=True)
+    assert worst < tol
