@@ -88,6 +88,10 @@ struct ListedPlanDev {
     //   3: Bt operands from global memory, half the waves
     //   4, 5 (float32 only): as 1 and 2 with the hit groups software-pipelined
     //   6, 7: as 1 and 2 with non-temporal hints on the streamed data
+    //   8, 9: as 1 and 2 with all operand loads of a hit group issued before
+    //      its MFMAs (scheduling barrier)
+    //   10, 11 / 12, 13 (float32 only): as 8 and 9 with 6 / 8 hits per slot
+    //      per group and two accumulators (8 hits: LDS reads after the barrier)
     int variant = 0;
     const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
     const int64_t *j_off = nullptr;      // [ntiles + 1]

@@ -117,7 +117,8 @@ __device__ inline void decode(const void *ent, int idx, int &pa, int &sl) {
     }
 }
 
-template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE, bool NTH>
+template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE, bool NTH,
+          int G, bool SB, int MAXACC>
 __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductOperands ops,
                                                     Epilogue ep) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -135,6 +136,8 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     static_assert(!MF64 || (B == 4 && CMAX == 4 && sizeof(T) == 8), "MFMA64 path: double, b = 4");
     static_assert(!BD || MFMA || MF64, "direct Bt operands: MFMA paths only");
     static_assert(!PIPE || (MFMA && BD), "pipelined hit groups: float32 MFMA path with direct operands");
+    static_assert(G == 4 || (MFMA && BD && !PIPE && SB), "larger hit groups: float32 MFMA path with direct operands");
+    static_assert(!SB || ((MFMA || MF64) && BD), "scheduling barrier: MFMA paths with direct operands");
 
     const int ntiles = plan.ntiles;
     const int nt8 = (ntiles + 7) & ~7;
@@ -204,11 +207,11 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     const int64_t j0 = plan.j_off[tile];
     const int nj = (int)(plan.j_off[tile + 1] - j0);
     // accumulator weights of this tile (one system per tile in batches)
-    double wq[4];
+    double wq[MAXACC];
     {
         const int sys = ep.row_sys ? ep.row_sys[row0] : 0;
 #pragma unroll
-        for (int qa = 0; qa < 4; ++qa) wq[qa] = (ep.row_sys && ep.coef_sys[qa]) ? ep.coef_sys[qa][sys] : ep.coef[qa];
+        for (int qa = 0; qa < MAXACC; ++qa) wq[qa] = (ep.row_sys && ep.coef_sys[qa]) ? ep.coef_sys[qa][sys] : ep.coef[qa];
     }
     const int4 *recs = reinterpret_cast<const int4 *>(plan.j_rec);
     const T *BtV = reinterpret_cast<const T *>(ops.bt_val);
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             /* lanes without an output read element 0 and drop the value */          \
             OFF[q_] = VAL[q_] ? (cb_ + op_) * BB + er[q_] * B + es[q_] : 0;           \
             if (Prev) PRV[q_] = ld_stream<NTH>(Prev + OFF[q_]);                       \
-            _Pragma("unroll") for (int qa_ = 0; qa_ < 4; ++qa_)                       \
+            _Pragma("unroll") for (int qa_ = 0; qa_ < MAXACC; ++qa_)                  \
                 if (qa_ < ep.nacc) ACCV[q_][qa_] = ld_stream<NTH>(ep.acc[qa_] + OFF[q_]); \
         }                                                                             \
     } while (0)
@@ -290,7 +293,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
         int64_t off[NE];
         bool valid[NE];
         T prev[NE];
-        double acc[NE][4];
+        double acc[NE][MAXACC];
     };
     Set S0, S1;
     S0.rb = make_int4(0, -1, -1, 0);
@@ -426,6 +429,42 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
                 acc += acc1;
                 it = groups * 4;
             }
+            // G hits per slot at a time: all operand loads issued before the
+            // MFMAs (one wait per G hits); G > 4 alternates two accumulators
+            if constexpr (G > 4) {
+                f32x4 acc2 = {0.f, 0.f, 0.f, 0.f};
+                for (; it + G <= iters; it += G) {
+                    lds_u8 *ap[G];
+                    b_u8 *bp[G];
+#pragma unroll
+                    for (int u = 0; u < G; ++u) addr(grp + 4 * (it + u), ap[u], bp[u]);
+                    f32x4 a[G], bb[G];
+                    // keep every global load of the group ahead of its MFMAs
+                    // (the scheduler would otherwise interleave them to save
+                    // registers, leaving one or two loads in flight); with
+                    // G > 6 the LDS reads of A follow the barrier, next to
+                    // their MFMAs, to stay within 128 registers
+#pragma unroll
+                    for (int u = 0; u < G; ++u) {
+                        if constexpr (G <= 6) a[u] = *(lds_f4 *)ap[u];
+                        bb[u] = *(b_f4 *)bp[u];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    if constexpr (G > 6) {
+#pragma unroll
+                        for (int u = 0; u < G; ++u) a[u] = *(lds_f4 *)ap[u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < G; ++u) {
+                        f32x4 &c = (u & 1) ? acc2 : acc;
+                        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][0], bb[u][0], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][1], bb[u][1], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][2], bb[u][2], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][3], bb[u][3], c, 0, 0, 0);
+                    }
+                }
+                acc += acc2;
+            }
             // four hits per slot at a time: all LDS reads issued before the MFMAs
             for (; it + 4 <= iters; it += 4) {
                 lds_u8 *ap[4];
@@ -438,6 +477,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
                     a[u] = *(lds_f4 *)ap[u];
                     bb[u] = *(b_f4 *)bp[u];
                 }
+                if constexpr (SB) __builtin_amdgcn_sched_barrier(0);  // all loads before the MFMAs
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][0], bb[u][0], acc, 0, 0, 0);
@@ -529,6 +569,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
                         a[u] = *(lds_d *)ap[u];
                         bb[u] = *(b_d *)bp[u];
                     }
+                    if constexpr (SB) __builtin_amdgcn_sched_barrier(0);  // all loads before the MFMAs
 #pragma unroll
                     for (int u = 0; u < 8; u += 2) {
                         acc = __builtin_amdgcn_mfma_f64_4x4x4f64(a[u], bb[u], acc, 0, 0, 0);
@@ -602,7 +643,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             st_stream<NTH>(reinterpret_cast<T *>(ops.c_out) + C.off[q], o);
             const double od = (double)o;
 #pragma unroll
-            for (int qa = 0; qa < 4; ++qa)
+            for (int qa = 0; qa < MAXACC; ++qa)
                 if (qa < ep.nacc) st_stream<NTH>(ep.acc[qa] + C.off[q], C.acc[q][qa] + wq[qa] * od);
             if (ep.hist) st_stream<NTH>(reinterpret_cast<T *>(ep.hist) + C.off[q], o);
             if (row0 + ei[q] == jc && er[q] == es[q]) tr += od;
@@ -633,14 +674,29 @@ struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
     static constexpr int MODE = (B == 4 && CMAX == 4) ? (std::is_same<T, float>::value ? 1 : 2) : 0;
     static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int COUNT = MODE == 0 ? 1 : 8;
-    // variants 4 and 5 (pipelined hit groups) exist for float32 only
+    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 14 : 10);
+    // variants 4, 5 (pipelined hit groups) and 10-13 (6- and 8-hit groups) are float32 only
     static bool ok(int v) { return v >= 0 && v < COUNT && (MODE == 1 || (v != 4 && v != 5)); }
 };
 
+template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE, bool NTH,
+          int G, bool SB, int MAXACC>
+hipError_t launch_a(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                    hipStream_t st, size_t *lds_out);
+
+// accumulator count is a template bound: chains with at most one float64
+// sum (the common case) keep fewer registers
 template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE = false,
-          bool NTH = false>
+          bool NTH = false, int G = 4, bool SB = false>
 hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                    hipStream_t st, size_t *lds_out) {
+    if (ep.nacc <= 1) return launch_a<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, 1>(plan, ops, ep, st, lds_out);
+    return launch_a<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, 4>(plan, ops, ep, st, lds_out);
+}
+
+template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE, bool NTH,
+          int G, bool SB, int MAXACC>
+hipError_t launch_a(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
                     hipStream_t st, size_t *lds_out) {
     const size_t lds = listed_lds<T, B, NW, EW, BD>(plan).total;
     if (lds_out) {
@@ -648,7 +704,7 @@ hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const
         return hipSuccess;
     }
     if (plan.ntiles == 0) return hipSuccess;
-    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH>;
+    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, MAXACC>;
     static int raised_device = -1;
     static size_t raised_to = 0;
     int dev = 0;
@@ -660,7 +716,7 @@ hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const
         raised_to = lds;
     }
     const int nt8 = (plan.ntiles + 7) & ~7;
-    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH>), dim3(nt8), dim3(64 * NW), lds, st,
+    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, MAXACC>), dim3(nt8), dim3(64 * NW), lds, st,
                        plan, ops, ep);
     return hipGetLastError();
 }
@@ -688,6 +744,20 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
                 return hipErrorInvalidValue;
             case 6: return launch_v<T, B, CMAX, NW, MODE, EW, true, false, true>(plan, ops, ep, st, lds_out);
             case 7: return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true, false, true>(plan, ops, ep, st, lds_out);
+            case 8: return launch_v<T, B, CMAX, NW, MODE, EW, true, false, false, 4, true>(plan, ops, ep, st, lds_out);
+            case 9: return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true, false, false, 4, true>(plan, ops, ep, st, lds_out);
+            case 10:
+                if constexpr (MODE == 1) return launch_v<T, B, CMAX, NW, MODE, EW, true, false, false, 6, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 11:
+                if constexpr (MODE == 1) return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true, false, false, 6, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 12:
+                if constexpr (MODE == 1) return launch_v<T, B, CMAX, NW, MODE, EW, true, false, false, 8, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 13:
+                if constexpr (MODE == 1) return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true, false, false, 8, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
     }

@@ -103,23 +103,25 @@ def test_chebyshev_chain_parity(gpu_ctx, spec, precision, tol):
         assert np.max(np.abs(got - ref)) < tol, (precision, q)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", list(range(14)))
 @pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
 def test_chain_kernel_variants(gpu_ctx, monkeypatch, variant, precision, tol):
     # every variant of the b = 4 chain kernel, forced, against the oracle
     monkeypatch.setenv("CHESS_LISTED_VARIANT", str(variant))
-    if precision == "f64" and variant in (4, 5):  # float32-only variants
+    if precision == "f64" and variant in (4, 5, 10, 11, 12, 13):  # float32-only variants
         with pytest.raises(ChessError):
             chain_case(gpu_ctx, SYS4, 70, precision)
         return
     # SYS4: short hit lists (the remainder loop); SYSL: the cutoffs of the
     # 80 000-row workload, ~70 hits per output block (several pipelined groups)
+    # one float64 sum (the kernels specialised for at most one) and two
     for spec in (SYS4, SYSL):
-        s, accs, mom, acc_o, mom_o = chain_case(gpu_ctx, spec, 70, precision)
-        assert np.max(np.abs(mom - mom_o)) < tol * s.n
-        for q in range(2):
-            ref = bm(s.pat_k).to_block(acc_o[q])
-            assert np.max(np.abs(accs[q].cpu().numpy() - ref)) < tol, (variant, precision, q, spec)
+        for nq in (1, 2):
+            s, accs, mom, acc_o, mom_o = chain_case(gpu_ctx, spec, 70, precision, nq=nq)
+            assert np.max(np.abs(mom - mom_o)) < tol * s.n
+            for q in range(nq):
+                ref = bm(s.pat_k).to_block(acc_o[q])
+                assert np.max(np.abs(accs[q].cpu().numpy() - ref)) < tol, (variant, precision, q, spec)
     s2 = system(*SYS4, kT=0.02)
     _, info = chess_fermi_operator(gpu_ctx, dt(s2.H), gpat(s2.pat_h), dt(s2.S), gpat(s2.pat_h),
                                    gpat(s2.pat_k), s2.n_electrons, s2.kT, precision=precision,
@@ -128,7 +130,7 @@ def test_chain_kernel_variants(gpu_ctx, monkeypatch, variant, precision, tol):
 
 
 def test_chain_kernel_variant_out_of_range(gpu_ctx, monkeypatch):
-    monkeypatch.setenv("CHESS_LISTED_VARIANT", "9")
+    monkeypatch.setenv("CHESS_LISTED_VARIANT", "14")
     with pytest.raises(ChessError):
         chain_case(gpu_ctx, SYS4, 10, "f32")
 
