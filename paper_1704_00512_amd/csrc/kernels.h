@@ -92,6 +92,8 @@ struct ListedPlanDev {
     //      its MFMAs (scheduling barrier)
     //   10, 11 / 12, 13 (float32 only): as 8 and 9 with 6 / 8 hits per slot
     //      per group and two accumulators (8 hits: LDS reads after the barrier)
+    //   14 / 15 (float32 only): as 12 / 10 with the last group padded past
+    //      the lists (one wait per group, no remainder loops)
     int variant = 0;
     const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
     const int64_t *j_off = nullptr;      // [ntiles + 1]

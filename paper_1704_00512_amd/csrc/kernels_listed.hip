@@ -118,7 +118,7 @@ __device__ inline void decode(const void *ent, int idx, int &pa, int &sl) {
 }
 
 template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE, bool NTH,
-          int G, bool SB, int MAXACC>
+          int G, bool SB, int MAXACC, bool PAD>
 __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductOperands ops,
                                                     Epilogue ep) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -126,6 +126,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     constexpr int NT = 64 * NW;
     constexpr bool MFMA = MODE == 1;
     constexpr bool MF64 = MODE == 2;
+    constexpr int kEntMax = kEntWords * 64 * 4 / (2 * EW);  // entries in a wave's list area
     constexpr int NE = (MFMA || MF64) ? 1 : (CMAX * BB + 63) / 64;
     // BD: MFMA operands of Bt come straight from global memory (L1/L2) and
     // Bt rows are not staged in LDS
@@ -137,6 +138,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     static_assert(!BD || MFMA || MF64, "direct Bt operands: MFMA paths only");
     static_assert(!PIPE || (MFMA && BD), "pipelined hit groups: float32 MFMA path with direct operands");
     static_assert(G == 4 || (MFMA && BD && !PIPE && SB), "larger hit groups: float32 MFMA path with direct operands");
+    static_assert(!PAD || G > 4, "padded hit groups: larger groups only");
     static_assert(!SB || ((MFMA || MF64) && BD), "scheduling barrier: MFMA paths with direct operands");
 
     const int ntiles = plan.ntiles;
@@ -370,12 +372,15 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             // row, finite, so the product is exactly zero)
             auto addr = [&](int hh, lds_u8 *&ap, b_u8 *&bp) {
                 uint32_t pa, sl;
+                // slots past their list read inside the wave's entry area
+                // (the value is not used)
+                const int ix = min(omine + hh, kEntMax - 1);
                 if constexpr (EW == 1) {
-                    const uint32_t e = reinterpret_cast<const uint16_t *>(entw)[omine + hh];
+                    const uint32_t e = reinterpret_cast<const uint16_t *>(entw)[ix];
                     pa = e & 0xFFu;
                     sl = e >> 8;
                 } else {
-                    const uint32_t e = reinterpret_cast<const uint32_t *>(entw)[omine + hh];
+                    const uint32_t e = reinterpret_cast<const uint32_t *>(entw)[ix];
                     pa = e & 0xFFFFu;
                     sl = e >> 16;
                 }
@@ -433,7 +438,9 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             // MFMAs (one wait per G hits); G > 4 alternates two accumulators
             if constexpr (G > 4) {
                 f32x4 acc2 = {0.f, 0.f, 0.f, 0.f};
-                for (; it + G <= iters; it += G) {
+                // PAD: the last group runs past the lists (zero products), so a
+                // column waits once per G hits and never in the loops below
+                for (; PAD ? it < iters : it + G <= iters; it += G) {
                     lds_u8 *ap[G];
                     b_u8 *bp[G];
 #pragma unroll
@@ -537,12 +544,15 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
             double acc = 0.0;
             auto addr = [&](int hh, lds_u8 *&ap, b_u8 *&bp) {
                 uint32_t pa, sl;
+                // slots past their list read inside the wave's entry area
+                // (the value is not used)
+                const int ix = min(omine + hh, kEntMax - 1);
                 if constexpr (EW == 1) {
-                    const uint32_t e = reinterpret_cast<const uint16_t *>(entw)[omine + hh];
+                    const uint32_t e = reinterpret_cast<const uint16_t *>(entw)[ix];
                     pa = e & 0xFFu;
                     sl = e >> 8;
                 } else {
-                    const uint32_t e = reinterpret_cast<const uint32_t *>(entw)[omine + hh];
+                    const uint32_t e = reinterpret_cast<const uint32_t *>(entw)[ix];
                     pa = e & 0xFFFFu;
                     sl = e >> 16;
                 }
@@ -674,28 +684,28 @@ struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
     static constexpr int MODE = (B == 4 && CMAX == 4) ? (std::is_same<T, float>::value ? 1 : 2) : 0;
     static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 14 : 10);
-    // variants 4, 5 (pipelined hit groups) and 10-13 (6- and 8-hit groups) are float32 only
+    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 16 : 10);
+    // variants 4, 5 (pipelined hit groups) and 10-15 (6- and 8-hit groups) are float32 only
     static bool ok(int v) { return v >= 0 && v < COUNT && (MODE == 1 || (v != 4 && v != 5)); }
 };
 
 template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE, bool NTH,
-          int G, bool SB, int MAXACC>
+          int G, bool SB, int MAXACC, bool PAD>
 hipError_t launch_a(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
                     hipStream_t st, size_t *lds_out);
 
 // accumulator count is a template bound: chains with at most one float64
 // sum (the common case) keep fewer registers
 template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE = false,
-          bool NTH = false, int G = 4, bool SB = false>
+          bool NTH = false, int G = 4, bool SB = false, bool PAD = false>
 hipError_t launch_v(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
                     hipStream_t st, size_t *lds_out) {
-    if (ep.nacc <= 1) return launch_a<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, 1>(plan, ops, ep, st, lds_out);
-    return launch_a<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, 4>(plan, ops, ep, st, lds_out);
+    if (ep.nacc <= 1) return launch_a<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, 1, PAD>(plan, ops, ep, st, lds_out);
+    return launch_a<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, 4, PAD>(plan, ops, ep, st, lds_out);
 }
 
 template <typename T, int B, int CMAX, int NW, int MODE, int EW, bool BD, bool PIPE, bool NTH,
-          int G, bool SB, int MAXACC>
+          int G, bool SB, int MAXACC, bool PAD>
 hipError_t launch_a(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
                     hipStream_t st, size_t *lds_out) {
     const size_t lds = listed_lds<T, B, NW, EW, BD>(plan).total;
@@ -704,7 +714,7 @@ hipError_t launch_a(const ListedPlanDev &plan, const ProductOperands &ops, const
         return hipSuccess;
     }
     if (plan.ntiles == 0) return hipSuccess;
-    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, MAXACC>;
+    const void *fn = (const void *)k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, MAXACC, PAD>;
     static int raised_device = -1;
     static size_t raised_to = 0;
     int dev = 0;
@@ -716,7 +726,7 @@ hipError_t launch_a(const ListedPlanDev &plan, const ProductOperands &ops, const
         raised_to = lds;
     }
     const int nt8 = (plan.ntiles + 7) & ~7;
-    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, MAXACC>), dim3(nt8), dim3(64 * NW), lds, st,
+    hipLaunchKernelGGL((k_listed<T, B, CMAX, NW, MODE, EW, BD, PIPE, NTH, G, SB, MAXACC, PAD>), dim3(nt8), dim3(64 * NW), lds, st,
                        plan, ops, ep);
     return hipGetLastError();
 }
@@ -757,6 +767,12 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
                 return hipErrorInvalidValue;
             case 13:
                 if constexpr (MODE == 1) return launch_v<T, B, CMAX, 2 * NW, MODE, EW, true, false, false, 8, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 14:
+                if constexpr (MODE == 1) return launch_v<T, B, CMAX, NW, MODE, EW, true, false, false, 8, true, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 15:
+                if constexpr (MODE == 1) return launch_v<T, B, CMAX, NW, MODE, EW, true, false, false, 6, true, true>(plan, ops, ep, st, lds_out);
                 return hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
