@@ -167,8 +167,10 @@ typedef struct {
  *                 lo, hi, s_lo, s_hi, n_pl, n_pl_s, penalty, tr_ks (of K at
  *                 mu_trial[1]), ne_chain = N(mu_trial[1]); ms_total and
  *                 ms_chain_kernel are those of the whole call
- * The batch form does not widen bounds: a system failing Eq. 6 or the growth
- * test returns CHESS_E_BOUNDS.  opts apply to every system.
+ * A system whose bounds fail Eq. 6 or the growth test is redone, after the
+ * others, in a batch of its own with the Gershgorin interval (info->fallback
+ * bit 0 set); CHESS_E_BOUNDS only if the Gershgorin interval itself fails.
+ * opts apply to every system.
  */
 typedef struct {
     const chess_matrix *H;

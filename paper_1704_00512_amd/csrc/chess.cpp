@@ -748,7 +748,9 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
         lp->dev.variant = lp->tuned_variant;
         return;
     }
-    lp->dev.variant = 0;
+    // untimed default: operands from global memory behind a scheduling
+    // barrier (float32), the same with 8 waves (float64); variant 0 otherwise
+    lp->dev.variant = (nvar > 1) ? (dtype == 1 ? 8 : 2) : 0;
     if (nvar == 1 || n_pl < 64) return;  // too short a chain to time variants on
     hipStream_t st = ctx->stream;
     DevBuf out(vbytes(lp->c, dtype));
@@ -1972,6 +1974,8 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
     // per system: Eq. 6 and growth checks, mu from the moments, N at the trial mu
     std::vector<double> mu_star(nsys), ne_tr(3 * (size_t)nsys), pen(nsys);
     std::vector<int> iters(nsys);
+    std::vector<char> failed(nsys, 0);
+    std::vector<int> failed_pos;
     for (int s = 0; s < nsys; ++s) {
         std::vector<double> t(npl[s]);
         for (int k = 0; k < npl[s]; ++k) t[k] = hmom[(size_t)k * nsys + s];
@@ -1979,8 +1983,17 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
         const double p = hostmath::penalty_trace(t, -200.0, &fit_err);
         const bool pen_valid = fit_err * (double)PKs[s]->n() < 0.1;
         pen[s] = pen_valid ? p : nan;
-        if (!growth_ok(t, PKs[s]->n()) || (pen_valid && std::fabs(p) > 0.5))
-            CHESS_THROW(CHESS_E_BOUNDS, "system %d: bounds [%g, %g] fail Eq. 6 or the growth test", idx[s], lo[s], hi[s]);
+        if (!growth_ok(t, PKs[s]->n()) || (pen_valid && std::fabs(p) > 0.5)) {
+            // rejected bounds: this system is redone below with the
+            // Gershgorin interval (unless that is what failed)
+            const bool rigorous = o.bounds_mode == CHESS_BOUNDS_GERSHGORIN &&
+                                  !(std::isfinite(o.bounds[0]) && std::isfinite(o.bounds[1]));
+            if (rigorous)
+                CHESS_THROW(CHESS_E_BOUNDS, "system %d: Gershgorin bounds [%g, %g] fail Eq. 6 or the growth test", idx[s], lo[s], hi[s]);
+            failed[s] = 1;
+            failed_pos.push_back(s);
+            continue;
+        }
         hostmath::CountFunction N;
         N.init(t, lo[s], hi[s], kTs[s], o.smearing == CHESS_ERFC ? 0 : 1);
         const double tol_ne = o.tol_ne > 0 ? o.tol_ne : 1e-8 * nes[s];
@@ -2003,7 +2016,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
         post_transform(ctx, PK, F, accK[q].as<double>(), PS, Ss.as<double>(), Kb.as<double>());
         for (int s = 0; s < nsys; ++s) {
             chess_matrix *Ko = items[idx[s]].K_out[q];
-            if (!Ko) continue;
+            if (!Ko || failed[s]) continue;
             HIPCHECK(hipMemcpyAsync(Ko->val, Kb.as<double>() + offK[s] * bb, sizeof(double) * PKs[s]->nnzb * bb, hipMemcpyDeviceToDevice, st));
             if (q == 1 && items[idx[s]].info) {
                 const EmbedMap *es = get_embed(ctx, PSs[s], PKs[s], "S in the kernel pattern");
@@ -2021,6 +2034,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
     DevBuf Sinv(kbytes);
     transpose_into(ctx, PK, accSinv.as<double>(), Sinv.as<double>());
     for (int s = 0; s < nsys; ++s) {
+        if (failed[s]) continue;
         const chess_batch_item &it = items[idx[s]];
         const size_t bytes = sizeof(double) * PKs[s]->nnzb * bb;
         if (it.Sinvhalf_out) HIPCHECK(hipMemcpyAsync(it.Sinvhalf_out->val, F.X.as<double>() + offK[s] * bb, bytes, hipMemcpyDeviceToDevice, st));
@@ -2047,6 +2061,30 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
         }
     }
     HIPCHECK(hipStreamSynchronize(st));
+    if (!failed_pos.empty()) {
+        // the rejected systems again, as a batch of their own, with the
+        // rigorous Gershgorin interval and the trial mu of the first attempt
+        std::vector<chess_batch_item> sub;
+        for (int s : failed_pos) {
+            chess_batch_item it = items[idx[s]];
+            for (int q = 0; q < 3; ++q) it.mu_trial[q] = mus[s][q];
+            sub.push_back(it);
+        }
+        chess_opts o2 = o;
+        o2.bounds_mode = CHESS_BOUNDS_GERSHGORIN;
+        o2.bounds[0] = o2.bounds[1] = nan;
+        std::vector<int> sidx(sub.size());
+        for (size_t k = 0; k < sub.size(); ++k) sidx[k] = (int)k;
+        batched_group(ctx, sidx, sub.data(), o2, use_graph, ms_chains);
+        for (int s : failed_pos)
+            if (chess_info *info = items[idx[s]].info) {
+                info->fallback |= 1;
+                info->reexpansions += 1;
+                info->pred_lo = preds[s][0];
+                info->pred_hi = preds[s][1];
+                info->pred_mu = preds[s][2];
+            }
+    }
 }
 
 static void fermi_batched(chess_ctx *ctx, int32_t nsys, const chess_batch_item *items,

@@ -103,3 +103,22 @@ def test_batched_errors(gpu_ctx):
         chess_fermi_operator_batched(gpu_ctx, args, bounds_mode="lanczos")
     with pytest.raises(ChessError):
         chess_fermi_operator_batched(gpu_ctx, [], bounds_mode="lanczos")
+
+
+def test_batched_rejected_bounds_fall_back_to_gershgorin(gpu_ctx):
+    # bounds far inside the spectra: every system fails the growth test and
+    # is redone with its Gershgorin interval
+    ss = systems()[:3]
+    args = batch_args(ss)
+    res = chess_fermi_operator_batched(gpu_ctx, args, precision="f64", bounds=(-1.0, -0.6),
+                                       n_pl=120, n_pl_s=40)
+    for s, a, r in zip(ss, args, res):
+        inf = r["info"]
+        assert inf["fallback"] & 1
+        assert inf["lo"] < -1.0 and inf["hi"] > -0.6
+        H, S, P = bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k)
+        Ko, _ = opl.fermi_operator(H, S, P, s.n_electrons, s.kT,
+                                   s_bounds_=(inf["s_lo"], inf["s_hi"]), n_pl_s=40,
+                                   h_bounds=(inf["lo"], inf["hi"]), n_pl=120,
+                                   mu=a["mu_trial"][1])
+        assert np.max(np.abs(r["K"][1].cpu().numpy() - Ko)) < 1e-10
