@@ -748,9 +748,10 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
         lp->dev.variant = lp->tuned_variant;
         return;
     }
-    // untimed default: operands from global memory behind a scheduling
-    // barrier (float32), the same with 8 waves (float64); variant 0 otherwise
-    lp->dev.variant = (nvar > 1) ? (dtype == 1 ? 8 : 2) : 0;
+    // untimed default: b = 4, operands from global memory behind a scheduling
+    // barrier (float32) or the same with 8 waves (float64); b = 9 float32, the
+    // MFMA kernel with 8 waves; variant 0 otherwise
+    lp->dev.variant = nvar == 1 ? 0 : (b == 4 && dtype == 1) ? 8 : 2;
     if (nvar == 1 || n_pl < 64) return;  // too short a chain to time variants on
     hipStream_t st = ctx->stream;
     DevBuf out(vbytes(lp->c, dtype));

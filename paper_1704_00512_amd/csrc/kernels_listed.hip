@@ -679,6 +679,169 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     }
 }
 
+// float32, b = 9, tiles of <= 2 rows, on v_mfma_f32_4x4x1f32: the 9 x 9
+// output block of (row i, column j) is a 3 x 3 grid of 3 x 3 sub-blocks, one
+// per MFMA slot (slots 0..8; lane q = 3 and slots 9..15 carry zeros).  Slot
+// s = 3 I' + J' takes row 3 I' + q of A[i, l] as its A operand and row
+// 3 J' + q of Bt[j, l] as its B operand, so nine MFMAs (k = 0..8) form one
+// 9 x 9 x 9 block product; register v of lane (s, q) ends as element
+// (3 I' + v, 3 J' + q).  Rows of the tile are taken one after the other;
+// hit lists and the epilogue are those of k_listed.
+template <int NW, int EW, int MAXACC>
+__global__ __launch_bounds__(64 * NW) void k_listed9(ListedPlanDev plan, ProductOperands ops,
+                                                     Epilogue ep) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int BB = 81;
+    constexpr int NT = 64 * NW;
+    constexpr int kEntMax = kEntWords * 64 * 4 / (2 * EW);
+    const int ntiles = plan.ntiles;
+    const int nt8 = (ntiles + 7) & ~7;
+    const int w = blockIdx.x;
+    const int tile = (w & 7) * (nt8 >> 3) + (w >> 3);
+    if (tile >= ntiles) return;
+    const ListedLds L = listed_lds<float, 9, NW, EW, true>(plan);
+    const int row0 = plan.tile_row0[tile];
+    const int c = plan.tile_row0[tile + 1] - row0;
+    const int64_t ab0 = ops.a_rp[row0];
+    float *As = reinterpret_cast<float *>(smem + L.a);
+    {
+        const int nab = (int)(ops.a_rp[row0 + c] - ab0);
+        const float *Ag = reinterpret_cast<const float *>(ops.a_val) + ab0 * BB;
+        for (int x = threadIdx.x; x < nab * BB; x += NT) As[x] = Ag[x];
+        for (int x = threadIdx.x; x < BB; x += NT) As[(size_t)plan.lds_ablocks * BB + x] = 0.f;
+    }
+    int rstart[2];
+    int64_t cbase_i[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        rstart[i] = (i < c) ? (int)(ops.a_rp[row0 + i] - ab0) : 0;
+        cbase_i[i] = (i < c) ? ops.c_rp[row0 + i] : 0;
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    unsigned char *entw = smem + L.wave + (size_t)wave * (L.wave_bt + L.wave_ent) + L.wave_bt;
+    const int slot = lane >> 2, q = lane & 3;
+    const bool live = slot < 9 && q < 3;
+    const int arow = 3 * (slot / 3) + q, bcol = 3 * (slot % 3) + q;
+    typedef __attribute__((address_space(3))) const float lds_f;
+    lds_f *zrow = (lds_f *)(As + (size_t)plan.lds_ablocks * BB);
+    const int64_t j0 = plan.j_off[tile];
+    const int nj = (int)(plan.j_off[tile + 1] - j0);
+    const int4 *recs = reinterpret_cast<const int4 *>(plan.j_rec);
+    const float *BtV = reinterpret_cast<const float *>(ops.bt_val);
+    const float *Prev = reinterpret_cast<const float *>(ep.prev);
+    const uint32_t *E32 = reinterpret_cast<const uint32_t *>(plan.entries);
+    double wq[MAXACC];
+    {
+        const int sys = ep.row_sys ? ep.row_sys[row0] : 0;
+#pragma unroll
+        for (int qa = 0; qa < MAXACC; ++qa) wq[qa] = (ep.row_sys && ep.coef_sys[qa]) ? ep.coef_sys[qa][sys] : ep.coef[qa];
+    }
+    double tr = 0.0;
+    for (int jj = wave; jj < nj; jj += NW) {
+        const int4 ra = recs[2 * (j0 + jj)], rb = recs[2 * (j0 + jj) + 1];
+        const int jc = ra.x, rowc = ra.y;
+        int cnt[2], eoff[2];
+        cnt[0] = rb.x & 0xFF;
+        cnt[1] = (rb.x >> 8) & 0xFF;
+        eoff[0] = 0;
+        eoff[1] = cnt[0];
+        {
+            // this column's hit lists -> the wave's LDS area
+            const int tot = cnt[0] + cnt[1];
+            const int nwv = ((tot * 2 * EW + 3) / 4 + 63) >> 6;
+            const uint32_t *es = E32 + ((int64_t)ra.w * 2 * EW) / 4 + lane;
+            uint32_t *e32 = reinterpret_cast<uint32_t *>(entw) + lane;
+#pragma unroll
+            for (int v = 0; v < kEntWords; ++v)
+                if (v < nwv) e32[v * 64] = es[v * 64];
+        }
+        wave_sync_lds();
+        const float *bbase = BtV + (int64_t)rowc * BB + (live ? bcol : 0) * 9;
+        for (int i = 0; i < c; ++i) {
+            const uint32_t word = (uint32_t)rb.y;
+            const unsigned op = (word >> (i * 16)) & 0xFFFFu;
+            if (op == 0xFFFFu) continue;  // (i, j) not in the output pattern
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
+            lds_f *abase = (lds_f *)(As + (size_t)rstart[i] * BB + arow * 9);
+            const int n = cnt[i];
+            for (int h = 0; h < n; h += 2) {
+                // two hits per wait (the second past the list reads zeros)
+                float a0[9], b0[9], a1[9], b1[9];
+                int pa0, sl0, pa1, sl1;
+                decode<EW>(entw, min(eoff[i] + h, kEntMax - 1), pa0, sl0);
+                decode<EW>(entw, min(eoff[i] + h + 1, kEntMax - 1), pa1, sl1);
+                const bool ok1 = h + 1 < n;
+                lds_f *ap0 = live ? abase + pa0 * BB : zrow;
+                lds_f *ap1 = (live && ok1) ? abase + pa1 * BB : zrow;
+                const float *bp0 = bbase + (int64_t)sl0 * BB;
+                const float *bp1 = bbase + (int64_t)(ok1 ? sl1 : sl0) * BB;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    a0[k] = ap0[k];
+                    b0[k] = bp0[k];
+                    a1[k] = ap1[k];
+                    b1[k] = bp1[k];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    acc = __builtin_amdgcn_mfma_f32_4x4x1f32(a0[k], b0[k], acc, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f32_4x4x1f32(a1[k], b1[k], acc2, 0, 0, 0);
+                }
+            }
+            acc += acc2;
+            if (live) {
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    const int r = 3 * (slot / 3) + v, cc = bcol;
+                    const int64_t off = (cbase_i[i] + op) * BB + r * 9 + cc;
+                    float o = (float)ep.alpha * acc[v];
+                    if (Prev) o = fmaf((float)ep.beta, Prev[off], o);
+                    reinterpret_cast<float *>(ops.c_out)[off] = o;
+                    const double od = (double)o;
+#pragma unroll
+                    for (int qa = 0; qa < MAXACC; ++qa)
+                        if (qa < ep.nacc) ep.acc[qa][off] = ep.acc[qa][off] + wq[qa] * od;
+                    if (ep.hist) reinterpret_cast<float *>(ep.hist)[off] = o;
+                    if (row0 + i == jc && r == cc) tr += od;
+                }
+            }
+        }
+        wave_sync_lds();
+    }
+    if (ep.trace_partial) {
+        const double sm = bsum<NT>(tr);
+        if (threadIdx.x == 0) ep.trace_partial[tile] = sm;
+    }
+}
+
+template <int NW, int EW, int MAXACC>
+hipError_t launch_9(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                    hipStream_t st, size_t *lds_out) {
+    const size_t lds = listed_lds<float, 9, NW, EW, true>(plan).total;
+    if (lds_out) {
+        *lds_out = lds;
+        return hipSuccess;
+    }
+    if (plan.ntiles == 0) return hipSuccess;
+    const void *fn = (const void *)k_listed9<NW, EW, MAXACC>;
+    static int raised_device = -1;
+    static size_t raised_to = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (lds > 65536 && (raised_device != dev || raised_to < lds)) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        raised_device = dev;
+        raised_to = lds;
+    }
+    const int nt8 = (plan.ntiles + 7) & ~7;
+    hipLaunchKernelGGL((k_listed9<NW, EW, MAXACC>), dim3(nt8), dim3(64 * NW), lds, st, plan, ops, ep);
+    return hipGetLastError();
+}
+
 template <typename T, int B, int CMAX>
 struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
@@ -738,8 +901,19 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
     constexpr int NW = V::NW;
     constexpr int MODE = V::MODE;
     if constexpr (MODE == 0) {
-        if (plan.variant != 0) return hipErrorInvalidValue;
-        return launch_v<T, B, CMAX, NW, MODE, EW, false>(plan, ops, ep, st, lds_out);
+        if (plan.variant == 0) return launch_v<T, B, CMAX, NW, MODE, EW, false>(plan, ops, ep, st, lds_out);
+        if constexpr (std::is_same<T, float>::value && B == 9 && CMAX == 2) {
+            // 9 x 9 blocks on the matrix cores
+            if (plan.variant == 1 || plan.variant == 2) {
+                if (ep.nacc <= 1) {
+                    if (plan.variant == 1) return launch_9<4, EW, 1>(plan, ops, ep, st, lds_out);
+                    return launch_9<8, EW, 1>(plan, ops, ep, st, lds_out);
+                }
+                if (plan.variant == 1) return launch_9<4, EW, 4>(plan, ops, ep, st, lds_out);
+                return launch_9<8, EW, 4>(plan, ops, ep, st, lds_out);
+            }
+        }
+        return hipErrorInvalidValue;
     } else {
         switch (plan.variant) {
             case 0: return launch_v<T, B, CMAX, NW, MODE, EW, false>(plan, ops, ep, st, lds_out);
@@ -815,11 +989,13 @@ hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
 }
 
 int listed_product_variants(int dtype, int b, const ListedPlanDev &plan) {
+    if (b == 9 && dtype == 1 && plan.cmax == 2) return 3;  // VALU, MFMA with 4 or 8 waves
     if (b != 4 || plan.cmax != 4) return 1;
     return dtype == 0 ? LVariant<double, 4, 4>::COUNT : LVariant<float, 4, 4>::COUNT;
 }
 
 bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int v) {
+    if (b == 9 && dtype == 1 && plan.cmax == 2) return v >= 0 && v < 3;
     if (b != 4 || plan.cmax != 4) return v == 0;
     return dtype == 0 ? LVariant<double, 4, 4>::ok(v) : LVariant<float, 4, 4>::ok(v);
 }

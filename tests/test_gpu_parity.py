@@ -129,6 +129,18 @@ def test_chain_kernel_variants(gpu_ctx, monkeypatch, variant, precision, tol):
     assert info["kernel_variant"] == variant
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("nq", [1, 2])
+def test_b9_chain_kernel_variants(gpu_ctx, monkeypatch, variant, nq):
+    # float32 9 x 9 blocks: vector ALU (0) and matrix cores (1, 2), against the oracle
+    monkeypatch.setenv("CHESS_LISTED_VARIANT", str(variant))
+    s, accs, mom, acc_o, mom_o = chain_case(gpu_ctx, SYS9, 70, "f32", nq=nq)
+    assert np.max(np.abs(mom - mom_o)) < TOL32 * s.n
+    for q in range(nq):
+        ref = bm(s.pat_k).to_block(acc_o[q])
+        assert np.max(np.abs(accs[q].cpu().numpy() - ref)) < TOL32, (variant, nq, q)
+
+
 def test_chain_kernel_variant_out_of_range(gpu_ctx, monkeypatch):
     monkeypatch.setenv("CHESS_LISTED_VARIANT", "16")
     with pytest.raises(ChessError):
