@@ -144,7 +144,7 @@ struct ListedPlan {
     std::vector<int32_t> breaks;     // rows where a tile must start (batches: system starts)
     std::vector<int32_t> tile_row0;  // host copy, ntiles + 1
     ListedPlanDev dev;
-    DevBuf d_tile_row0, d_j_off, d_j_rec, d_entries;
+    DevBuf d_tile_row0, d_j_off, d_j_rec, d_entries, d_lean_rec, d_lean_ent;
 };
 
 // Learned bound / mu predictor loaded by chess_model_load (layout of the
@@ -442,15 +442,21 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
     const int ntiles = (int)tile_row0.size();
     tile_row0.push_back(A->nb);
     P->tile_row0 = tile_row0;
+    // hit lists with free slot assignment (float32, b = 4, one-byte positions;
+    // Bt rows of at most 128 blocks, so position 255 is outside every row)
+    const bool want_lean = dtype == 1 && b == 4 && cmax == 4 && ew == 1;
     struct TileOut {
         std::vector<int32_t> rec;      // 8 per column; entry offsets relative to the tile
         std::vector<uint16_t> ent;     // entry_width 1
         std::vector<uint32_t> ent32;   // entry_width 2
+        std::vector<int32_t> lrec;     // free slot assignment: 8 per column, rounds relative to the tile
+        std::vector<uint8_t> lent;     // 32 bytes per round
         bool overflow = false;
     };
     std::vector<TileOut> outs(ntiles);
     auto work = [&](int t0, int t1) {
         std::vector<int32_t> cols;
+        std::vector<uint16_t> hits[4];
         for (int t = t0; t < t1; ++t) {
             TileOut &o = outs[t];
             const int row0 = tile_row0[t], c = tile_row0[t + 1] - row0;
@@ -462,6 +468,7 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
                 int32_t counts = 0;
                 uint32_t pos01 = 0xFFFFFFFFu, pos23 = 0xFFFFFFFFu;
                 int total = 0;
+                for (auto &h : hits) h.clear();
                 for (int i = 0; i < c; ++i) {
                     const int row = row0 + i;
                     const int64_t q = C->find(row, j);
@@ -484,9 +491,10 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
                         } else {
                             const uint32_t ra = (uint32_t)(pa - A->rp[row]);
                             const uint32_t rbt = (uint32_t)(pb - Bt->rp[j]);
-                            if (ew == 1)
+                            if (ew == 1) {
                                 o.ent.push_back((uint16_t)(ra | (rbt << 8)));
-                            else
+                                if (want_lean) hits[i].push_back((uint16_t)(ra | (rbt << 8)));
+                            } else
                                 o.ent32.push_back(ra | (rbt << 16));
                             ++n;
                             ++pa;
@@ -502,6 +510,47 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
                 if (ew == 1 && (o.ent.size() & 1)) o.ent.push_back(0);
                 o.rec.insert(o.rec.end(), {j, (int32_t)Bt->rp[j], (int32_t)(Bt->rp[j + 1] - Bt->rp[j]),
                                            (int32_t)first, counts, (int32_t)pos01, (int32_t)pos23, 0});
+                if (want_lean) {
+                    // fewest rounds R with sum_i ceil(cnt_i / R) <= 16 slots; row i
+                    // gets n_i = ceil(cnt_i / R) consecutive slots, slot k of the
+                    // row takes hits k, k + n_i, ...; R is padded to an even count
+                    int R = 0, n[4] = {0, 0, 0, 0};
+                    if (total > 0) {
+                        for (R = (total + 15) / 16;; ++R) {
+                            int need = 0;
+                            for (int i = 0; i < 4; ++i) need += ((int)hits[i].size() + R - 1) / R;
+                            if (need <= 16) break;
+                        }
+                        for (int i = 0; i < 4; ++i) n[i] = ((int)hits[i].size() + R - 1) / R;
+                        R = (R + 1) & ~1;
+                    }
+                    const int64_t lfirst = (int64_t)o.lent.size() / 32;
+                    const size_t base = o.lent.size();
+                    o.lent.resize(base + (size_t)R * 32);
+                    for (int r = 0; r < R; ++r) {
+                        uint8_t *pa = &o.lent[base + (size_t)r * 32], *pb = pa + 16;
+                        for (int sl = 0; sl < 16; ++sl) {
+                            pa[sl] = 0;
+                            pb[sl] = 255;  // past the list: A's first block times zeros
+                        }
+                        int s0 = 0;
+                        for (int i = 0; i < 4; ++i) {
+                            for (int k = 0; k < n[i]; ++k) {
+                                const size_t h = (size_t)k + (size_t)n[i] * r;
+                                if (h < hits[i].size()) {
+                                    pa[s0 + k] = (uint8_t)(hits[i][h] & 0xFF);
+                                    pb[s0 + k] = (uint8_t)(hits[i][h] >> 8);
+                                }
+                            }
+                            s0 += n[i];
+                        }
+                    }
+                    if (R > 32) o.overflow = true;  // not reached: at most 4 x 128 hits
+                    o.lrec.insert(o.lrec.end(), {j, (int32_t)Bt->rp[j], (int32_t)(Bt->rp[j + 1] - Bt->rp[j]),
+                                                 (int32_t)lfirst,
+                                                 R | (n[0] << 8) | (n[1] << 13) | (n[2] << 18) | (n[3] << 23),
+                                                 (int32_t)pos01, (int32_t)pos23, 0});
+                }
             }
         }
     };
@@ -514,7 +563,7 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
     }
     for (auto &th : pool) th.join();
     std::vector<int64_t> j_off(ntiles + 1, 0);
-    int64_t tot_ent = 0, tot_col = 0;
+    int64_t tot_ent = 0, tot_col = 0, tot_rounds = 0;
     for (int t = 0; t < ntiles; ++t) {
         if (outs[t].overflow) {
             ctx->lplans.push_back(std::move(P));
@@ -523,7 +572,9 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
         j_off[t + 1] = j_off[t] + (int64_t)outs[t].rec.size() / 8;
         tot_col += (int64_t)outs[t].rec.size() / 8;
         tot_ent += ew == 1 ? (int64_t)outs[t].ent.size() : (int64_t)outs[t].ent32.size();
+        tot_rounds += (int64_t)outs[t].lent.size() / 32;
     }
+    const bool lean = want_lean && tot_rounds < ((int64_t)1 << 31);
     if (tot_ent >= ((int64_t)1 << 31)) {
         ctx->lplans.push_back(std::move(P));
         return ctx->lplans.back().get();
@@ -532,7 +583,10 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
     std::vector<uint16_t> ent;
     std::vector<uint32_t> ent32;
     if (ew == 1) ent.resize((size_t)tot_ent); else ent32.resize((size_t)tot_ent);
-    int64_t ebase = 0;
+    std::vector<int32_t> lrec(lean ? (size_t)tot_col * 8 : 0);
+    // padded so that the last column's 4-word-per-lane prefetch stays inside
+    std::vector<uint8_t> lent(lean ? (size_t)tot_rounds * 32 + 1024 : 0, 0);
+    int64_t ebase = 0, lbase = 0;
     for (int t = 0; t < ntiles; ++t) {
         TileOut &o = outs[t];
         const size_t nrec = o.rec.size() / 8;
@@ -540,7 +594,18 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
             int32_t *r = &rec[(size_t)(j_off[t] + x) * 8];
             std::copy(o.rec.begin() + 8 * x, o.rec.begin() + 8 * x + 8, r);
             r[3] = (int32_t)(r[3] + ebase);
+            if (lean) {
+                int32_t *lr = &lrec[(size_t)(j_off[t] + x) * 8];
+                std::copy(o.lrec.begin() + 8 * x, o.lrec.begin() + 8 * x + 8, lr);
+                lr[3] = (int32_t)(lr[3] + lbase);
+            }
         }
+        if (lean) {
+            std::copy(o.lent.begin(), o.lent.end(), lent.begin() + lbase * 32);
+            lbase += (int64_t)o.lent.size() / 32;
+        }
+        std::vector<int32_t>().swap(o.lrec);
+        std::vector<uint8_t>().swap(o.lent);
         if (ew == 1) {
             std::copy(o.ent.begin(), o.ent.end(), ent.begin() + ebase);
             ebase += (int64_t)o.ent.size();
@@ -559,6 +624,10 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
     upload(P->d_j_off, j_off, st);
     upload(P->d_j_rec, rec, st);
     if (ew == 1) upload(P->d_entries, ent, st); else upload(P->d_entries, ent32, st);
+    if (lean) {
+        upload(P->d_lean_rec, lrec, st);
+        upload(P->d_lean_ent, lent, st);
+    }
     HIPCHECK(hipStreamSynchronize(st));
     ListedPlanDev &d = P->dev;
     d.ntiles = ntiles;
@@ -571,6 +640,11 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
     d.j_off = P->d_j_off.as<int64_t>();
     d.j_rec = P->d_j_rec.as<int32_t>();
     d.entries = P->d_entries.p;
+    if (lean) {
+        d.lean_rec = P->d_lean_rec.as<int32_t>();
+        d.lean_ent = P->d_lean_ent.as<uint8_t>();
+    }
+    for (int t = 0; t < ntiles; ++t) d.max_cols = std::max<int>(d.max_cols, (int)(j_off[t + 1] - j_off[t]));
     P->usable = listed_product_lds_bytes(dtype, b, d) <= 160 * 1024;
     ctx->lplans.push_back(std::move(P));
     return ctx->lplans.back().get();
@@ -748,10 +822,17 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
         lp->dev.variant = lp->tuned_variant;
         return;
     }
-    // untimed default: b = 4, operands from global memory behind a scheduling
-    // barrier (float32) or the same with 8 waves (float64); b = 9 float32, the
-    // MFMA kernel with 8 waves; variant 0 otherwise
-    lp->dev.variant = nvar == 1 ? 0 : (b == 4 && dtype == 1) ? 8 : 2;
+    // untimed default: b = 4 float32, the slots shared among the tile rows
+    // with the prefetch after the last group's loads (or, without that plan,
+    // operands from global memory behind a scheduling barrier); b = 4 float64,
+    // operands from global memory with 8 waves; b = 9 float32, the MFMA kernel
+    // with 8 waves; variant 0 otherwise
+    if (nvar == 1)
+        lp->dev.variant = 0;
+    else if (b == 4 && dtype == 1)
+        lp->dev.variant = listed_product_variant_ok(dtype, b, lp->dev, 20) ? 20 : 8;
+    else
+        lp->dev.variant = 2;
     if (nvar == 1 || n_pl < 64) return;  // too short a chain to time variants on
     hipStream_t st = ctx->stream;
     DevBuf out(vbytes(lp->c, dtype));

@@ -94,11 +94,25 @@ struct ListedPlanDev {
     //      per group and two accumulators (8 hits: LDS reads after the barrier)
     //   14 / 15 (float32 only): as 12 / 10 with the last group padded past
     //      the lists (one wait per group, no remainder loops)
+    //   16-19 (float32 only, plans with lean_rec): the 16 MFMA slots shared
+    //      freely among the tile rows (k_lean); 8 waves with 8-round groups,
+    //      12 waves with 8-round groups, 8 waves with 4-round groups, 16 waves
+    //      with 4-round groups
     int variant = 0;
     const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
     const int64_t *j_off = nullptr;      // [ntiles + 1]
     const int32_t *j_rec = nullptr;      // [total_j * 8]
     const void *entries = nullptr;
+    // Free slot assignment (float32, b = 4; null otherwise): per column a
+    // record of 8 int32 {j, Bt row start, Bt row length, first round,
+    // R | n_0 << 8 | n_1 << 13 | n_2 << 18 | n_3 << 23, out pos rows 0|1,
+    // 2|3, 0}: R rounds (even, <= 32) of the 16 MFMA slots, tile row i on n_i
+    // consecutive slots (sum <= 16).  Per round 32 bytes: the position in
+    // A row i of each slot's hit, then its position in Bt row j (255 past
+    // the slot's list).
+    const int32_t *lean_rec = nullptr;
+    const uint8_t *lean_ent = nullptr;
+    int max_cols = 0;  // most output columns of a tile
 };
 
 hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,

@@ -842,13 +842,324 @@ hipError_t launch_9(const ListedPlanDev &plan, const ProductOperands &ops, const
     return hipGetLastError();
 }
 
+// float32, b = 4, tiles of <= 4 rows, on v_mfma_f32_4x4x1f32 with the 16 MFMA
+// slots shared freely among the tile rows (plan.lean_rec / lean_ent).  With
+// four slots fixed per row (k_listed) a column costs max_i ceil(cnt_i / 4)
+// rounds of all 16 slots, so short or absent rows leave slots idle; here the
+// host gives row i n_i consecutive slots (sum <= 16) so that the rounds
+// R = max_i ceil(cnt_i / n_i) are as few as possible, and lays the hits out
+// per round as 16 one-byte positions in the A rows, then 16 in the Bt row.
+// A slot past its list reads its row's first A block and Bt position 255,
+// outside the row: the buffer load returns zeros there, so the padded
+// products add exact zeros and the loop has no per-hit conditions.  Each lane
+// needs two LDS byte reads and two address operations per hit.  After the
+// rounds the slots' partial blocks go to the wave's LDS area and each output
+// lane sums those of its row's slots.  Groups of GM rounds issue all loads
+// before their MFMAs (one wait per group); prefetching of records, hit lists
+// and epilogue operands one column ahead and the epilogue follow k_listed.
+struct LeanLds {
+    size_t a, rec, wave, total;
+};
+
+// k_lean LDS: the A tile, the tile's column records, then 1 KB per wave (hit
+// lists of the column, then the slots' partial blocks)
+template <int NW>
+__host__ __device__ inline LeanLds lean_lds(const ListedPlanDev &p) {
+    LeanLds L;
+    L.a = 0;
+    L.rec = al16((size_t)p.lds_ablocks * 64);
+    L.wave = L.rec + al16((size_t)p.max_cols * 32);
+    L.total = L.wave + (size_t)NW * 1024;
+    return L;
+}
+
+template <int NW, int GM, bool LATE, int MAXACC>
+__global__ __launch_bounds__(64 * NW) void k_lean(ListedPlanDev plan, ProductOperands ops, Epilogue ep) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int NT = 64 * NW;
+    static_assert(GM == 4 || GM == 8, "rounds per group");
+    const int ntiles = plan.ntiles;
+    const int nt8 = (ntiles + 7) & ~7;
+    const int w = blockIdx.x;
+    const int tile = (w & 7) * (nt8 >> 3) + (w >> 3);
+    if (tile >= ntiles) return;
+    const LeanLds L = lean_lds<NW>(plan);
+    const int row0 = plan.tile_row0[tile];
+    const int c = plan.tile_row0[tile + 1] - row0;
+    const int64_t ab0 = ops.a_rp[row0];
+    const int64_t j0 = plan.j_off[tile];
+    const int nj = (int)(plan.j_off[tile + 1] - j0);
+    float *As = reinterpret_cast<float *>(smem + L.a);
+    {
+        // tile rows of A and the tile's column records -> LDS (records in
+        // LDS keep their loads out of the in-order vector memory queue)
+        const int n16 = (int)(ops.a_rp[row0 + c] - ab0) * 4;
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(reinterpret_cast<const float *>(ops.a_val) + ab0 * 16);
+        u32x4 *dst = reinterpret_cast<u32x4 *>(As);
+        for (int x = threadIdx.x; x < n16; x += NT) dst[x] = src[x];
+        const i32x4 *rsrc = reinterpret_cast<const i32x4 *>(plan.lean_rec) + 2 * j0;
+        i32x4 *rdst = reinterpret_cast<i32x4 *>(smem + L.rec);
+        for (int x = threadIdx.x; x < 2 * nj; x += NT) rdst[x] = rsrc[x];
+    }
+    // first A block of each tile row in the LDS tile (named values, not an
+    // array: a per-lane index into an array would go through scratch memory)
+    const int rs0 = 0;
+    const int rs1 = (1 < c) ? (int)(ops.a_rp[row0 + 1] - ab0) : 0;
+    const int rs2 = (2 < c) ? (int)(ops.a_rp[row0 + 2] - ab0) : 0;
+    const int rs3 = (3 < c) ? (int)(ops.a_rp[row0 + 3] - ab0) : 0;
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    unsigned char *entw = smem + L.wave + (size_t)wave * 1024;
+    // MFMA operand lane: slot and row q of its blocks; output lane: element
+    // (er, es) of tile row oi
+    const int slot = lane >> 2, q = lane & 3;
+    const int oi = lane >> 4, er = (lane >> 2) & 3, es = lane & 3;
+    const int64_t cb_mine = (oi < c) ? ops.c_rp[row0 + oi] : 0;
+    double wq[MAXACC > 0 ? MAXACC : 1];
+    {
+        const int sys = ep.row_sys ? ep.row_sys[row0] : 0;
+#pragma unroll
+        for (int qa = 0; qa < MAXACC; ++qa) wq[qa] = (ep.row_sys && ep.coef_sys[qa]) ? ep.coef_sys[qa][sys] : ep.coef[qa];
+    }
+    typedef __attribute__((address_space(3))) const i32x4 lds_i4;
+    const lds_i4 *recs = (const lds_i4 *)(smem + L.rec);
+    const float *BtV = reinterpret_cast<const float *>(ops.bt_val);
+    const float *Prev = reinterpret_cast<const float *>(ep.prev);
+    const uint32_t *E32 = reinterpret_cast<const uint32_t *>(plan.lean_ent);
+    double tr = 0.0;
+    typedef __attribute__((address_space(3))) const unsigned char lds_u8;
+    typedef __attribute__((address_space(3))) const f32x4 lds_f4;
+
+    // The prefetch loads below are unconditional (past the last column they
+    // re-read the last record; unused words of a hit list re-read its first
+    // word; a missing T_{k-1} reads T_k, a missing sum the first one), so
+    // that no branch joins make the compiler wait for them early.
+    const float *PrevL = Prev ? Prev : reinterpret_cast<const float *>(ops.a_val);
+    constexpr int NACC = MAXACC > 0 ? MAXACC : 1;
+    const double *AccL[NACC];
+#pragma unroll
+    for (int qa = 0; qa < NACC; ++qa) AccL[qa] = (qa < ep.nacc) ? ep.acc[qa] : ep.acc[0];
+    struct Set {
+        i32x4 ra, rb;
+        uint32_t ew[kEntWords];
+        int64_t off;
+        bool live, valid;
+        float prev;
+        double acc[NACC];
+    };
+    // record of column JJ (nj >= 1)
+    auto lrec = [&](int JJ, Set &S) __attribute__((always_inline)) {
+        const int jl = min(JJ, nj - 1);
+        S.ra = recs[2 * jl];
+        S.rb = recs[2 * jl + 1];
+        S.live = JJ < nj;
+    };
+    // hit lists (R rounds of 32 bytes, at most 1 KB), then the epilogue
+    // operands of the column in S
+    auto lrow = [&](Set &S) __attribute__((always_inline)) {
+        const int nwv = S.live ? ((S.rb.x & 0xFF) * 8 + 63) >> 6 : 0;
+        const uint32_t *src = E32 + (int64_t)S.ra.w * 8 + lane;
+#pragma unroll
+        for (int v = 0; v < kEntWords; ++v) S.ew[v] = src[(v < nwv ? v : 0) * 64];
+        const uint32_t word = (oi < 2) ? (uint32_t)S.rb.y : (uint32_t)S.rb.z;
+        const unsigned op = (word >> ((oi & 1) * 16)) & 0xFFFFu;
+        S.valid = S.live && oi < c && op != 0xFFFFu;
+        // lanes without an output read element 0 and drop the value
+        S.off = S.valid ? (cb_mine + op) * 16 + er * 4 + es : 0;
+        S.prev = PrevL[S.off];
+#pragma unroll
+        for (int qa = 0; qa < MAXACC; ++qa) S.acc[qa] = AccL[qa][S.off];
+    };
+
+    auto column = [&](Set &C, Set &N, int JJ) __attribute__((always_inline)) {
+        const int jc = C.ra.x;
+        const int rowc = __builtin_amdgcn_readfirstlane(C.ra.y);
+        const int lenc = __builtin_amdgcn_readfirstlane(C.ra.z);
+        const int rbx = __builtin_amdgcn_readfirstlane(C.rb.x);
+        // loads for column JJ + NW (into N), then the record of JJ + 2 NW
+        // (into C).  Vector memory loads complete in order, so every wait for
+        // a group's Bt operands also waits for all loads issued before them:
+        // LATE issues these after the Bt loads of the column's last group,
+        // so that they overlap that group's MFMAs, the row sums and the
+        // epilogue instead of delaying the column's first MFMA
+        auto prefetch = [&]() __attribute__((always_inline)) {
+            lrow(N);
+            lrec(JJ + 2 * NW, C);
+        };
+        if constexpr (!LATE) prefetch();
+        const int R = rbx & 0xFF;
+        {
+            // all four words (the area is 1 KB): no branches, no early waits
+            uint32_t *e32 = reinterpret_cast<uint32_t *>(entw) + lane;
+#pragma unroll
+            for (int v = 0; v < kEntWords; ++v) e32[v * 64] = C.ew[v];
+        }
+        wave_sync_lds();
+        const int n0 = (rbx >> 8) & 31, n1 = (rbx >> 13) & 31, n2 = (rbx >> 18) & 31, n3 = (rbx >> 23) & 31;
+        const int p1 = n0, p2 = p1 + n1, p3 = p2 + n2;
+        // first A block of this slot's row (slots past the last row's take
+        // row 3's, which is in the tile)
+        const int rs = slot >= p3 ? rs3 : slot >= p2 ? rs2 : slot >= p1 ? rs1 : rs0;
+        lds_u8 *a_base = (lds_u8 *)As + rs * 64 + q * 16;
+        lds_u8 *e_base = (lds_u8 *)entw + slot;
+        const __amdgpu_buffer_rsrc_t brs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(BtV + (int64_t)rowc * 16), (short)0, lenc * 64, 0x00020000);
+        const int boff = q * 16;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f}, acc2 = {0.f, 0.f, 0.f, 0.f};
+        auto group = [&](auto gg, auto hook, int r0) __attribute__((always_inline)) {
+            constexpr int GG = decltype(gg)::value;
+            constexpr bool HOOK = decltype(hook)::value;
+            lds_u8 *e0 = e_base + r0 * 32;
+            uint32_t av[GG], bv[GG];
+#pragma unroll
+            for (int u = 0; u < GG; ++u) {
+                av[u] = e0[u * 32];
+                bv[u] = e0[u * 32 + 16];
+            }
+            u32x4 bb[GG];
+            f32x4 a[GG];
+#pragma unroll
+            for (int u = 0; u < GG; ++u) {
+                bb[u] = __builtin_amdgcn_raw_buffer_load_b128(brs, (int)((bv[u] << 6) + boff), 0, 0);
+                if constexpr (GG <= 4) a[u] = *(lds_f4 *)(a_base + (av[u] << 6));
+            }
+            if constexpr (HOOK) prefetch();
+            // every global load of the group ahead of its MFMAs; with 8
+            // rounds the LDS reads of A follow, next to their MFMAs
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (GG > 4) {
+#pragma unroll
+                for (int u = 0; u < GG; ++u) a[u] = *(lds_f4 *)(a_base + (av[u] << 6));
+            }
+#pragma unroll
+            for (int u = 0; u < GG; ++u) {
+                f32x4 &cc = (u & 1) ? acc2 : acc;
+                const f32x4 b = __builtin_bit_cast(f32x4, bb[u]);
+                cc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][0], b[0], cc, 0, 0, 0);
+                cc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][1], b[1], cc, 0, 0, 0);
+                cc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][2], b[2], cc, 0, 0, 0);
+                cc = __builtin_amdgcn_mfma_f32_4x4x1f32(a[u][3], b[3], cc, 0, 0, 0);
+            }
+        };
+        // R (even) = GM m + t: m groups of GM rounds, then 4 (if t & 4, GM = 8)
+        // and 2 (if t & 2); LATE: the prefetch goes with the last group
+        using G2 = std::integral_constant<int, 2>;
+        using G4 = std::integral_constant<int, 4>;
+        using GF = std::integral_constant<int, GM>;
+        using NOH = std::integral_constant<bool, false>;
+        using LH = std::integral_constant<bool, LATE>;
+        const int m = R / GM, t = R % GM;
+        const bool has4 = GM > 4 && (t & 4) != 0, has2 = (t & 2) != 0;
+        const int mlast = (has4 || has2 || m == 0) ? m : m - 1;  // plain full groups
+        int r = 0;
+        for (int g = 0; g < mlast; ++g, r += GM) group(GF{}, NOH{}, r);
+        if (!has4 && !has2) {
+            if (m > 0) {
+                group(GF{}, LH{}, r);
+            } else if constexpr (LATE) {
+                prefetch();
+            }
+        } else {
+            if constexpr (GM > 4) {
+                if (has4) {
+                    if (has2) {
+                        group(G4{}, NOH{}, r);
+                    } else {
+                        group(G4{}, LH{}, r);
+                    }
+                    r += 4;
+                }
+            }
+            if (has2) group(G2{}, LH{}, r);
+        }
+        acc += acc2;
+        // partial block of each slot -> LDS (element (v, q) of slot s at
+        // float s * 16 + q * 4 + v); the hit lists there have been read
+        reinterpret_cast<f32x4 *>(entw)[lane] = acc;
+        wave_sync_lds();
+        const float *pl = reinterpret_cast<const float *>(entw);
+        int so = 0, no = n0;
+        if (oi == 1) { so = p1; no = n1; }
+        if (oi == 2) { so = p2; no = n2; }
+        if (oi == 3) { so = p3; no = n3; }
+        float y = 0.f;
+        for (int k = 0; k < no; ++k) y += pl[(so + k) * 16 + es * 4 + er];
+        wave_sync_lds();  // the area takes the next column's lists
+        // fused epilogue
+        if (C.valid) {
+            float o = (float)ep.alpha * y;
+            if (Prev) o = fmaf((float)ep.beta, C.prev, o);
+            reinterpret_cast<float *>(ops.c_out)[C.off] = o;
+            const double od = (double)o;
+#pragma unroll
+            for (int qa = 0; qa < MAXACC; ++qa)
+                if (qa < ep.nacc) ep.acc[qa][C.off] = C.acc[qa] + wq[qa] * od;
+            if (ep.hist) reinterpret_cast<float *>(ep.hist)[C.off] = o;
+            if (row0 + oi == jc && er == es) tr += od;
+        }
+    };
+    if (nj > 0) {
+        Set S0, S1;
+        int jj = wave;
+        lrec(jj, S0);
+        lrow(S0);
+        lrec(jj + NW, S1);
+        for (; jj < nj; jj += 2 * NW) {
+            column(S0, S1, jj);
+            if (jj + NW >= nj) break;
+            column(S1, S0, jj + NW);
+        }
+    }
+    if (ep.trace_partial) {
+        const double s = bsum<NT>(tr);
+        if (threadIdx.x == 0) ep.trace_partial[tile] = s;
+    }
+}
+
+template <int NW, int GM, bool LATE, int MAXACC>
+hipError_t launch_lean_a(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                         hipStream_t st, size_t *lds_out) {
+    const size_t lds = lean_lds<NW>(plan).total;
+    if (lds_out) {
+        *lds_out = lds;
+        return hipSuccess;
+    }
+    if (plan.ntiles == 0) return hipSuccess;
+    if (!plan.lean_rec || plan.entry_width != 1 || plan.cmax != 4) return hipErrorInvalidValue;
+    const void *fn = (const void *)k_lean<NW, GM, LATE, MAXACC>;
+    static int raised_device = -1;
+    static size_t raised_to = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (lds > 65536 && (raised_device != dev || raised_to < lds)) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        raised_device = dev;
+        raised_to = lds;
+    }
+    const int nt8 = (plan.ntiles + 7) & ~7;
+    hipLaunchKernelGGL((k_lean<NW, GM, LATE, MAXACC>), dim3(nt8), dim3(64 * NW), lds, st, plan, ops, ep);
+    return hipGetLastError();
+}
+
+template <int NW, int GM, bool LATE = false>
+hipError_t launch_lean(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                       hipStream_t st, size_t *lds_out) {
+    if (ep.nacc <= 0) return launch_lean_a<NW, GM, LATE, 0>(plan, ops, ep, st, lds_out);
+    if (ep.nacc == 1) return launch_lean_a<NW, GM, LATE, 1>(plan, ops, ep, st, lds_out);
+    return launch_lean_a<NW, GM, LATE, 4>(plan, ops, ep, st, lds_out);
+}
+
 template <typename T, int B, int CMAX>
 struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
     static constexpr int MODE = (B == 4 && CMAX == 4) ? (std::is_same<T, float>::value ? 1 : 2) : 0;
     static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 16 : 10);
-    // variants 4, 5 (pipelined hit groups) and 10-15 (6- and 8-hit groups) are float32 only
+    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 23 : 10);
+    // variants 4, 5 (pipelined hit groups), 10-15 (6- and 8-hit groups) and
+    // 16-22 (free slot assignment) are float32 only
     static bool ok(int v) { return v >= 0 && v < COUNT && (MODE == 1 || (v != 4 && v != 5)); }
 };
 
@@ -948,6 +1259,27 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
             case 15:
                 if constexpr (MODE == 1) return launch_v<T, B, CMAX, NW, MODE, EW, true, false, false, 6, true, true>(plan, ops, ep, st, lds_out);
                 return hipErrorInvalidValue;
+            case 16:
+                if constexpr (MODE == 1 && EW == 1) return launch_lean<8, 8>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 17:
+                if constexpr (MODE == 1 && EW == 1) return launch_lean<12, 8>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 18:
+                if constexpr (MODE == 1 && EW == 1) return launch_lean<8, 4>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 19:
+                if constexpr (MODE == 1 && EW == 1) return launch_lean<16, 4>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 20:
+                if constexpr (MODE == 1 && EW == 1) return launch_lean<8, 8, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 21:
+                if constexpr (MODE == 1 && EW == 1) return launch_lean<8, 4, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 22:
+                if constexpr (MODE == 1 && EW == 1) return launch_lean<16, 4, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }
     }
@@ -997,6 +1329,7 @@ int listed_product_variants(int dtype, int b, const ListedPlanDev &plan) {
 bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int v) {
     if (b == 9 && dtype == 1 && plan.cmax == 2) return v >= 0 && v < 3;
     if (b != 4 || plan.cmax != 4) return v == 0;
+    if (v >= 16 && !(dtype == 1 && plan.lean_rec && plan.entry_width == 1)) return false;
     return dtype == 0 ? LVariant<double, 4, 4>::ok(v) : LVariant<float, 4, 4>::ok(v);
 }
 
