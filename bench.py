@@ -304,17 +304,18 @@ def main():
     tflops = flops_launch * launches_call / (kern_ms * 1e-3) / 1e12
     t_hbm = bytes_call / (HBM_PEAK_GBS * 1e9)
     t_alu = flops_launch * launches_call / (FP32_PEAK_TFLOPS * 1e12)
-    bound = "hbm" if t_hbm >= t_alu else "alu"
+    bound = "hbm" if t_hbm >= t_alu else "mfma"
     avg_launch_ms = kern_ms / max(launches_call, 1)
     traffic = measured_traffic(args.workload)
     if bound == "hbm":
         roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(gbs / HBM_PEAK_GBS, 4))
     else:
-        roof = dict(bound="alu", achieved=round(tflops, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+        roof = dict(bound="mfma", achieved=round(tflops, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(tflops / FP32_PEAK_TFLOPS, 4))
-    roof.update(traffic=traffic, kernel=f"k_listed<float,4,4,...> (chain product), variant "
-                                        f"{info['kernel_variant']} chosen by timing",
+    kname = ("k_lean<...> (chain product, MFMA slots shared among tile rows)"
+             if 16 <= info["kernel_variant"] <= 23 else "k_listed<float,4,4,...> (chain product)")
+    roof.update(traffic=traffic, kernel=f"{kname}, variant {info['kernel_variant']} chosen by timing",
                 avg_launch_ms=round(avg_launch_ms, 4),
                 algorithmic_bytes_per_call=int(bytes_call), launches_per_call=launches_call,
                 flops_per_launch=flops_launch, achieved_gbs=round(gbs, 1),

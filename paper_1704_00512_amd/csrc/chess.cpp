@@ -574,7 +574,10 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
         tot_ent += ew == 1 ? (int64_t)outs[t].ent.size() : (int64_t)outs[t].ent32.size();
         tot_rounds += (int64_t)outs[t].lent.size() / 32;
     }
-    const bool lean = want_lean && tot_rounds < ((int64_t)1 << 31);
+    // the free-slot kernel addresses hit lists and float64 sums with 31-bit
+    // byte offsets
+    const bool lean = want_lean && tot_rounds * 32 + 1024 < ((int64_t)1 << 31) &&
+                      C->nnzb * 16 * 8 < ((int64_t)1 << 31);
     if (tot_ent >= ((int64_t)1 << 31)) {
         ctx->lplans.push_back(std::move(P));
         return ctx->lplans.back().get();

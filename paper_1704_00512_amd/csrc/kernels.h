@@ -98,6 +98,8 @@ struct ListedPlanDev {
     //      freely among the tile rows (k_lean); 8 waves with 8-round groups,
     //      12 waves with 8-round groups, 8 waves with 4-round groups, 16 waves
     //      with 4-round groups
+    //   20-22: as 16, 18, 19 with the next column's loads issued after the
+    //      last group's Bt loads; 23: as 21 with 10 waves (<= 96 VGPRs)
     int variant = 0;
     const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
     const int64_t *j_off = nullptr;      // [ntiles + 1]

@@ -873,8 +873,10 @@ __host__ __device__ inline LeanLds lean_lds(const ListedPlanDev &p) {
     return L;
 }
 
+// (10 waves: two workgroups per CU need 5 waves per SIMD, at most 96 VGPRs)
 template <int NW, int GM, bool LATE, int MAXACC>
-__global__ __launch_bounds__(64 * NW) void k_lean(ListedPlanDev plan, ProductOperands ops, Epilogue ep) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 10 ? 5 : 1)))
+void k_lean(ListedPlanDev plan, ProductOperands ops, Epilogue ep) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int NT = 64 * NW;
     static_assert(GM == 4 || GM == 8, "rounds per group");
@@ -916,7 +918,9 @@ __global__ __launch_bounds__(64 * NW) void k_lean(ListedPlanDev plan, ProductOpe
     // (er, es) of tile row oi
     const int slot = lane >> 2, q = lane & 3;
     const int oi = lane >> 4, er = (lane >> 2) & 3, es = lane & 3;
-    const int64_t cb_mine = (oi < c) ? ops.c_rp[row0 + oi] : 0;
+    // first output element of this lane's row (element offsets of the
+    // kernel pattern fit in 31 bits: checked when the plan is built)
+    const uint32_t cb_mine = (oi < c) ? (uint32_t)ops.c_rp[row0 + oi] * 16u + er * 4 + es : 0u;
     double wq[MAXACC > 0 ? MAXACC : 1];
     {
         const int sys = ep.row_sys ? ep.row_sys[row0] : 0;
@@ -927,7 +931,6 @@ __global__ __launch_bounds__(64 * NW) void k_lean(ListedPlanDev plan, ProductOpe
     const lds_i4 *recs = (const lds_i4 *)(smem + L.rec);
     const float *BtV = reinterpret_cast<const float *>(ops.bt_val);
     const float *Prev = reinterpret_cast<const float *>(ep.prev);
-    const uint32_t *E32 = reinterpret_cast<const uint32_t *>(plan.lean_ent);
     double tr = 0.0;
     typedef __attribute__((address_space(3))) const unsigned char lds_u8;
     typedef __attribute__((address_space(3))) const f32x4 lds_f4;
@@ -936,15 +939,25 @@ __global__ __launch_bounds__(64 * NW) void k_lean(ListedPlanDev plan, ProductOpe
     // re-read the last record; unused words of a hit list re-read its first
     // word; a missing T_{k-1} reads T_k, a missing sum the first one), so
     // that no branch joins make the compiler wait for them early.
-    const float *PrevL = Prev ? Prev : reinterpret_cast<const float *>(ops.a_val);
+    // Streamed operands go through buffer descriptors (32-bit offsets, one
+    // VGPR per address instead of a 64-bit pointer)
+    constexpr int kAll = 0x7FFFFFFF;
+    auto rsrc = [](const void *p) __attribute__((always_inline)) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, kAll, 0x00020000);
+    };
+    const __amdgpu_buffer_rsrc_t r_prev = rsrc(Prev ? ep.prev : ops.a_val);
+    const __amdgpu_buffer_rsrc_t r_out = rsrc(ops.c_out);
+    const __amdgpu_buffer_rsrc_t r_hist = rsrc(ep.hist ? ep.hist : ops.c_out);
+    const __amdgpu_buffer_rsrc_t r_ent = rsrc(plan.lean_ent);
     constexpr int NACC = MAXACC > 0 ? MAXACC : 1;
-    const double *AccL[NACC];
+    __amdgpu_buffer_rsrc_t r_acc[NACC];
 #pragma unroll
-    for (int qa = 0; qa < NACC; ++qa) AccL[qa] = (qa < ep.nacc) ? ep.acc[qa] : ep.acc[0];
+    for (int qa = 0; qa < NACC; ++qa) r_acc[qa] = rsrc((qa < ep.nacc) ? ep.acc[qa] : ep.acc[0]);
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
     struct Set {
         i32x4 ra, rb;
         uint32_t ew[kEntWords];
-        int64_t off;
+        uint32_t off;
         bool live, valid;
         float prev;
         double acc[NACC];
@@ -959,18 +972,21 @@ __global__ __launch_bounds__(64 * NW) void k_lean(ListedPlanDev plan, ProductOpe
     // hit lists (R rounds of 32 bytes, at most 1 KB), then the epilogue
     // operands of the column in S
     auto lrow = [&](Set &S) __attribute__((always_inline)) {
-        const int nwv = S.live ? ((S.rb.x & 0xFF) * 8 + 63) >> 6 : 0;
-        const uint32_t *src = E32 + (int64_t)S.ra.w * 8 + lane;
+        const int rbx = __builtin_amdgcn_readfirstlane(S.rb.x);
+        const int first = __builtin_amdgcn_readfirstlane(S.ra.w);
+        const int nwv = S.live ? ((rbx & 0xFF) * 8 + 63) >> 6 : 0;
 #pragma unroll
-        for (int v = 0; v < kEntWords; ++v) S.ew[v] = src[(v < nwv ? v : 0) * 64];
+        for (int v = 0; v < kEntWords; ++v)
+            S.ew[v] = __builtin_amdgcn_raw_buffer_load_b32(r_ent, lane * 4, first * 32 + (v < nwv ? v * 256 : 0), 0);
         const uint32_t word = (oi < 2) ? (uint32_t)S.rb.y : (uint32_t)S.rb.z;
         const unsigned op = (word >> ((oi & 1) * 16)) & 0xFFFFu;
         S.valid = S.live && oi < c && op != 0xFFFFu;
         // lanes without an output read element 0 and drop the value
-        S.off = S.valid ? (cb_mine + op) * 16 + er * 4 + es : 0;
-        S.prev = PrevL[S.off];
+        S.off = S.valid ? cb_mine + op * 16u : 0u;
+        S.prev = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r_prev, (int)(S.off * 4), 0, 0));
 #pragma unroll
-        for (int qa = 0; qa < MAXACC; ++qa) S.acc[qa] = AccL[qa][S.off];
+        for (int qa = 0; qa < MAXACC; ++qa)
+            S.acc[qa] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r_acc[qa], (int)(S.off * 8), 0, 0));
     };
 
     auto column = [&](Set &C, Set &N, int JJ) __attribute__((always_inline)) {
@@ -1085,18 +1101,23 @@ __global__ __launch_bounds__(64 * NW) void k_lean(ListedPlanDev plan, ProductOpe
         if (oi == 2) { so = p2; no = n2; }
         if (oi == 3) { so = p3; no = n3; }
         float y = 0.f;
-        for (int k = 0; k < no; ++k) y += pl[(so + k) * 16 + es * 4 + er];
+        {
+            const float *pk = pl + so * 16 + es * 4 + er;
+            for (int k = 0; k < no; ++k) y += pk[k * 16];
+        }
         wave_sync_lds();  // the area takes the next column's lists
         // fused epilogue
         if (C.valid) {
             float o = (float)ep.alpha * y;
             if (Prev) o = fmaf((float)ep.beta, C.prev, o);
-            reinterpret_cast<float *>(ops.c_out)[C.off] = o;
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, o), r_out, (int)(C.off * 4), 0, 0);
             const double od = (double)o;
 #pragma unroll
             for (int qa = 0; qa < MAXACC; ++qa)
-                if (qa < ep.nacc) ep.acc[qa][C.off] = C.acc[qa] + wq[qa] * od;
-            if (ep.hist) reinterpret_cast<float *>(ep.hist)[C.off] = o;
+                if (qa < ep.nacc)
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, C.acc[qa] + wq[qa] * od), r_acc[qa],
+                                                          (int)(C.off * 8), 0, 0);
+            if (ep.hist) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, o), r_hist, (int)(C.off * 4), 0, 0);
             if (row0 + oi == jc && er == es) tr += od;
         }
     };
@@ -1157,9 +1178,9 @@ struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
     static constexpr int MODE = (B == 4 && CMAX == 4) ? (std::is_same<T, float>::value ? 1 : 2) : 0;
     static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 23 : 10);
+    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 24 : 10);
     // variants 4, 5 (pipelined hit groups), 10-15 (6- and 8-hit groups) and
-    // 16-22 (free slot assignment) are float32 only
+    // 16-23 (free slot assignment) are float32 only
     static bool ok(int v) { return v >= 0 && v < COUNT && (MODE == 1 || (v != 4 && v != 5)); }
 };
 
@@ -1279,6 +1300,9 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
                 return hipErrorInvalidValue;
             case 22:
                 if constexpr (MODE == 1 && EW == 1) return launch_lean<16, 4, true>(plan, ops, ep, st, lds_out);
+                return hipErrorInvalidValue;
+            case 23:
+                if constexpr (MODE == 1 && EW == 1) return launch_lean<10, 4, true>(plan, ops, ep, st, lds_out);
                 return hipErrorInvalidValue;
             default: return hipErrorInvalidValue;
         }

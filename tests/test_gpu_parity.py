@@ -103,12 +103,12 @@ def test_chebyshev_chain_parity(gpu_ctx, spec, precision, tol):
         assert np.max(np.abs(got - ref)) < tol, (precision, q)
 
 
-@pytest.mark.parametrize("variant", list(range(23)))
+@pytest.mark.parametrize("variant", list(range(24)))
 @pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
 def test_chain_kernel_variants(gpu_ctx, monkeypatch, variant, precision, tol):
     # every variant of the b = 4 chain kernel, forced, against the oracle
     monkeypatch.setenv("CHESS_LISTED_VARIANT", str(variant))
-    if precision == "f64" and variant in (4, 5) + tuple(range(10, 23)):  # float32-only variants
+    if precision == "f64" and variant in (4, 5) + tuple(range(10, 24)):  # float32-only variants
         with pytest.raises(ChessError):
             chain_case(gpu_ctx, SYS4, 70, precision)
         return
@@ -142,7 +142,7 @@ def test_b9_chain_kernel_variants(gpu_ctx, monkeypatch, variant, nq):
 
 
 def test_chain_kernel_variant_out_of_range(gpu_ctx, monkeypatch):
-    monkeypatch.setenv("CHESS_LISTED_VARIANT", "23")
+    monkeypatch.setenv("CHESS_LISTED_VARIANT", "24")
     with pytest.raises(ChessError):
         chain_case(gpu_ctx, SYS4, 10, "f32")
 
