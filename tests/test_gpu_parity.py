@@ -129,6 +129,35 @@ def test_chain_kernel_variants(gpu_ctx, monkeypatch, variant, precision, tol):
     assert info["kernel_variant"] == variant
 
 
+# dense neighbourhoods: H rows of up to 118 blocks, up to 118 hits per output
+# block, so free slot assignment runs up to ~30 rounds per column (32 at most)
+SYSD = (200, 4, 6.4, 7.5, 24)
+
+
+@pytest.mark.parametrize("variant", [12, 16, 18, 20, 21])
+def test_chain_kernel_long_hit_lists(gpu_ctx, monkeypatch, variant):
+    s = system(*SYSD)
+    nb = s.pat_k.nb
+    assert np.diff(s.pat_h.row_ptr).max() <= 128  # b = 4 list plans take Bt rows of <= 128 blocks
+    kset = [set(s.pat_k.col_idx[s.pat_k.row_ptr[i]:s.pat_k.row_ptr[i + 1]]) for i in range(nb)]
+    hset = [set(s.pat_h.col_idx[s.pat_h.row_ptr[j]:s.pat_h.row_ptr[j + 1]]) for j in range(nb)]
+    hits = max(len(kset[i] & hset[j]) for i in range(0, nb, 7) for j in kset[i])
+    assert hits > 100
+    w = np.linalg.eigvalsh(bm(s.pat_h, s.H).csr().dense())
+    lo, hi = float(w[0]) - 0.1, float(w[-1]) + 0.1
+    monkeypatch.setenv("CHESS_LISTED_VARIANT", str(variant))
+    rng = np.random.default_rng(8)
+    coef = rng.standard_normal((2, 50)) / np.arange(1, 51)
+    accs, mom = chess_chebyshev(gpu_ctx, dt(s.H), gpat(s.pat_h), lo, hi, gpat(s.pat_k), 50, coef,
+                                precision="f32")
+    Mt = opl.scaled(bm(s.pat_h, s.H).csr(), lo, hi)
+    acc_o, mom_o = ocsr.chebyshev(Mt, bm(s.pat_k).pattern_csr(), 50, coef)
+    assert np.max(np.abs(mom - mom_o)) < TOL32 * s.n
+    for q in range(2):
+        ref = bm(s.pat_k).to_block(acc_o[q])
+        assert np.max(np.abs(accs[q].cpu().numpy() - ref)) < TOL32, (variant, q)
+
+
 @pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("nq", [1, 2])
 def test_b9_chain_kernel_variants(gpu_ctx, monkeypatch, variant, nq):
