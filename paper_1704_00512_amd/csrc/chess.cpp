@@ -648,6 +648,7 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
         d.lean_ent = P->d_lean_ent.as<uint8_t>();
     }
     for (int t = 0; t < ntiles; ++t) d.max_cols = std::max<int>(d.max_cols, (int)(j_off[t + 1] - j_off[t]));
+    d.off31 = C->nnzb * b * b * 8 < ((int64_t)1 << 31) && (tot_ent + 1024) * 2 * ew < ((int64_t)1 << 31);
     P->usable = listed_product_lds_bytes(dtype, b, d) <= 160 * 1024;
     ctx->lplans.push_back(std::move(P));
     return ctx->lplans.back().get();
@@ -829,11 +830,13 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
     // with the prefetch after the last group's loads (or, without that plan,
     // operands from global memory behind a scheduling barrier); b = 4 float64,
     // operands from global memory with 8 waves; b = 9 float32, the MFMA kernel
-    // with 8 waves; variant 0 otherwise
+    // with pipelined columns and 8 waves (or without); variant 0 otherwise
     if (nvar == 1)
         lp->dev.variant = 0;
     else if (b == 4 && dtype == 1)
         lp->dev.variant = listed_product_variant_ok(dtype, b, lp->dev, 20) ? 20 : 8;
+    else if (b == 9)
+        lp->dev.variant = listed_product_variant_ok(dtype, b, lp->dev, 3) ? 3 : 2;
     else
         lp->dev.variant = 2;
     if (nvar == 1 || n_pl < 64) return;  // too short a chain to time variants on

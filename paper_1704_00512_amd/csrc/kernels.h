@@ -100,6 +100,9 @@ struct ListedPlanDev {
     //      with 4-round groups
     //   20-22: as 16, 18, 19 with the next column's loads issued after the
     //      last group's Bt loads; 23: as 21 with 10 waves (<= 96 VGPRs)
+    // float32, b = 9 (tiles of 2 rows): 0 vector ALU; 1, 2: MFMA (k_listed9)
+    //   with 4 or 8 waves; 3, 4: MFMA with pipelined columns (k_lean9), 8 or
+    //   4 waves
     int variant = 0;
     const int32_t *tile_row0 = nullptr;  // [ntiles + 1]
     const int64_t *j_off = nullptr;      // [ntiles + 1]
@@ -115,6 +118,9 @@ struct ListedPlanDev {
     const int32_t *lean_rec = nullptr;
     const uint8_t *lean_ent = nullptr;
     int max_cols = 0;  // most output columns of a tile
+    // element offsets of the output pattern (in float64) and byte offsets of
+    // the hit lists fit in 31 bits (buffer-descriptor addressing)
+    bool off31 = false;
 };
 
 hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,

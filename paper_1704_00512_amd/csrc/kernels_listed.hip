@@ -1173,6 +1173,284 @@ hipError_t launch_lean(const ListedPlanDev &plan, const ProductOperands &ops, co
     return launch_lean_a<NW, GM, LATE, 4>(plan, ops, ep, st, lds_out);
 }
 
+struct Lean9Lds {
+    size_t a, rec, wave, total;
+};
+
+// k_lean9 LDS: the A tile and a zero block, the tile's column records, then
+// 1 KB per wave for the column's hit lists
+template <int NW>
+__host__ __device__ inline Lean9Lds lean9_lds(const ListedPlanDev &p) {
+    Lean9Lds L;
+    L.a = 0;
+    L.rec = al16((size_t)(p.lds_ablocks + 1) * 81 * sizeof(float));
+    L.wave = L.rec + al16((size_t)p.max_cols * 32);
+    L.total = L.wave + (size_t)NW * 1024;
+    return L;
+}
+
+// float32, b = 9, tiles of <= 2 rows: the MFMA block mapping of k_listed9
+// with the column pipelining of k_lean.  The tile's column records are copied
+// to LDS with the A tile; the hit lists and the epilogue operands of the next
+// column are loaded without branches, after the Bt loads of the column's last
+// hit group (vector memory loads complete in order, so loads issued earlier
+// would delay that group's MFMAs); Bt, hit lists and epilogue operands go
+// through buffer descriptors.  At most one float64 sum (MAXACC 0 or 1).
+template <int NW, int MAXACC>
+__global__ __launch_bounds__(64 * NW) void k_lean9(ListedPlanDev plan, ProductOperands ops, Epilogue ep) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int BB = 81;
+    constexpr int NT = 64 * NW;
+    constexpr int kEntMax = kEntWords * 64 * 2;  // 2-byte entries in a wave's 1 KB
+    static_assert(MAXACC <= 1, "at most one float64 sum");
+    const int ntiles = plan.ntiles;
+    const int nt8 = (ntiles + 7) & ~7;
+    const int w = blockIdx.x;
+    const int tile = (w & 7) * (nt8 >> 3) + (w >> 3);
+    if (tile >= ntiles) return;
+    const Lean9Lds L = lean9_lds<NW>(plan);
+    const int row0 = plan.tile_row0[tile];
+    const int c = plan.tile_row0[tile + 1] - row0;
+    const int64_t ab0 = ops.a_rp[row0];
+    const int64_t j0 = plan.j_off[tile];
+    const int nj = (int)(plan.j_off[tile + 1] - j0);
+    float *As = reinterpret_cast<float *>(smem + L.a);
+    {
+        const int nab = (int)(ops.a_rp[row0 + c] - ab0);
+        const float *Ag = reinterpret_cast<const float *>(ops.a_val) + ab0 * BB;
+        for (int x = threadIdx.x; x < nab * BB; x += NT) As[x] = Ag[x];
+        for (int x = threadIdx.x; x < BB; x += NT) As[(size_t)plan.lds_ablocks * BB + x] = 0.f;
+        const i32x4 *rsrc = reinterpret_cast<const i32x4 *>(plan.j_rec) + 2 * j0;
+        i32x4 *rdst = reinterpret_cast<i32x4 *>(smem + L.rec);
+        for (int x = threadIdx.x; x < 2 * nj; x += NT) rdst[x] = rsrc[x];
+    }
+    const int rs1 = (1 < c) ? (int)(ops.a_rp[row0 + 1] - ab0) : 0;
+    // element offsets of the kernel pattern fit in 31 bits (checked on the host)
+    const uint32_t cb0 = (uint32_t)ops.c_rp[row0];
+    const uint32_t cb1 = (1 < c) ? (uint32_t)ops.c_rp[row0 + 1] : 0u;
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    unsigned char *entw = smem + L.wave + (size_t)wave * 1024;
+    const int slot = lane >> 2, q = lane & 3;
+    const bool live = slot < 9 && q < 3;
+    const int arow = 3 * (slot / 3) + q, bcol = 3 * (slot % 3) + q;
+    typedef __attribute__((address_space(3))) const float lds_f;
+    typedef __attribute__((address_space(3))) const i32x4 lds_i4;
+    lds_f *zrow = (lds_f *)(As + (size_t)plan.lds_ablocks * BB);
+    lds_f *abase0 = (lds_f *)(As + arow * 9);
+    lds_f *abase1 = (lds_f *)(As + (size_t)rs1 * BB + arow * 9);
+    const lds_i4 *recs = (const lds_i4 *)(smem + L.rec);
+    // this lane's three outputs of a block: rows 3 (slot / 3) + v, column bcol
+    const uint32_t eo = (uint32_t)(3 * (slot / 3) * 9 + bcol);
+    const float *BtV = reinterpret_cast<const float *>(ops.bt_val);
+    const float *Prev = reinterpret_cast<const float *>(ep.prev);
+    double wq = 0.0;
+    if (MAXACC > 0) {
+        const int sys = ep.row_sys ? ep.row_sys[row0] : 0;
+        wq = (ep.row_sys && ep.coef_sys[0]) ? ep.coef_sys[0][sys] : ep.coef[0];
+    }
+    constexpr int kAll = 0x7FFFFFFF;
+    auto rsrc = [](const void *p, int n) __attribute__((always_inline)) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, n, 0x00020000);
+    };
+    const __amdgpu_buffer_rsrc_t r_prev = rsrc(Prev ? ep.prev : ops.a_val, kAll);
+    const __amdgpu_buffer_rsrc_t r_out = rsrc(ops.c_out, kAll);
+    const __amdgpu_buffer_rsrc_t r_hist = rsrc(ep.hist ? ep.hist : ops.c_out, kAll);
+    const __amdgpu_buffer_rsrc_t r_acc = rsrc(MAXACC > 0 ? (const void *)ep.acc[0] : ops.c_out, kAll);
+    const __amdgpu_buffer_rsrc_t r_ent = rsrc(plan.entries, kAll);
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    constexpr int NA = MAXACC > 0 ? 1 : 0;
+    struct Set {
+        i32x4 ra, rb;
+        uint32_t ew[kEntWords];
+        uint32_t off[2];
+        bool live, val[2];
+        float prev[2][3];
+        double acc[2][3 * NA + 1 - NA];
+    };
+    auto lrec = [&](int JJ, Set &S) __attribute__((always_inline)) {
+        const int jl = min(JJ, nj - 1);
+        S.ra = recs[2 * jl];
+        S.rb = recs[2 * jl + 1];
+        S.live = JJ < nj;
+    };
+    // hit lists, then the epilogue operands (unconditional loads: past the
+    // last column the last record, unused words the first one, lanes
+    // without an output element 0)
+    auto lrow = [&](Set &S) __attribute__((always_inline)) {
+        const int rbx = __builtin_amdgcn_readfirstlane(S.rb.x);
+        const int first = __builtin_amdgcn_readfirstlane(S.ra.w);
+        const int tot = (rbx & 0xFF) + ((rbx >> 8) & 0xFF);
+        const int nwv = S.live ? ((tot * 2 + 3) / 4 + 63) >> 6 : 0;
+#pragma unroll
+        for (int v = 0; v < kEntWords; ++v)
+            S.ew[v] = __builtin_amdgcn_raw_buffer_load_b32(r_ent, lane * 4, first * 2 + (v < nwv ? v * 256 : 0), 0);
+        const uint32_t word = (uint32_t)S.rb.y;
+        const uint32_t op0 = word & 0xFFFFu, op1 = word >> 16;
+        S.val[0] = S.live && live && op0 != 0xFFFFu;
+        S.val[1] = S.live && live && 1 < c && op1 != 0xFFFFu;
+        S.off[0] = S.val[0] ? (cb0 + op0) * 81u + eo : 0u;
+        S.off[1] = S.val[1] ? (cb1 + op1) * 81u + eo : 0u;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const uint32_t e = S.off[i] + v * 9;
+                S.prev[i][v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r_prev, (int)(e * 4), 0, 0));
+                if constexpr (MAXACC > 0)
+                    S.acc[i][v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r_acc, (int)(e * 8), 0, 0));
+            }
+    };
+    double tr = 0.0;
+    auto column = [&](Set &C, Set &N, int JJ) __attribute__((always_inline)) {
+        const int jc = C.ra.x;
+        const int rowc = __builtin_amdgcn_readfirstlane(C.ra.y);
+        const int lenc = __builtin_amdgcn_readfirstlane(C.ra.z);
+        const int rbx = __builtin_amdgcn_readfirstlane(C.rb.x);
+        auto prefetch = [&]() __attribute__((always_inline)) {
+            lrow(N);
+            lrec(JJ + 2 * NW, C);
+        };
+        const int cnt0 = rbx & 0xFF, cnt1 = (rbx >> 8) & 0xFF;
+        {
+            uint32_t *e32 = reinterpret_cast<uint32_t *>(entw) + lane;
+#pragma unroll
+            for (int v = 0; v < kEntWords; ++v) e32[v * 64] = C.ew[v];
+        }
+        wave_sync_lds();
+        const __amdgpu_buffer_rsrc_t brs = rsrc(BtV + (int64_t)rowc * BB, lenc * BB * 4);
+        const int boff = bcol * 36;
+        f32x4 a0 = {0.f, 0.f, 0.f, 0.f}, a0b = a0, a1 = a0, a1b = a0;
+        // two hits of one row per wait (the second past the list reads zeros)
+        auto grp = [&](auto ri, auto hook, int h) __attribute__((always_inline)) {
+            constexpr int RI = decltype(ri)::value;
+            constexpr bool HOOK = decltype(hook)::value;
+            const int n = RI ? cnt1 : cnt0;
+            const int eoff = RI ? cnt0 : 0;
+            lds_f *abase = RI ? abase1 : abase0;
+            f32x4 &acc = RI ? a1 : a0;
+            f32x4 &acc2 = RI ? a1b : a0b;
+            int pa0, sl0, pa1, sl1;
+            decode<1>(entw, min(eoff + h, kEntMax - 1), pa0, sl0);
+            decode<1>(entw, min(eoff + h + 1, kEntMax - 1), pa1, sl1);
+            const bool ok1 = h + 1 < n;
+            lds_f *ap0 = live ? abase + pa0 * BB : zrow;
+            lds_f *ap1 = (live && ok1) ? abase + pa1 * BB : zrow;
+            const int vo0 = sl0 * (BB * 4) + boff, vo1 = (ok1 ? sl1 : sl0) * (BB * 4) + boff;
+            float x0[9], y0[9], x1[9], y1[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                y0[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(brs, vo0 + 4 * k, 0, 0));
+                y1[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(brs, vo1 + 4 * k, 0, 0));
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                x0[k] = ap0[k];
+                x1[k] = ap1[k];
+            }
+            if constexpr (HOOK) prefetch();
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                acc = __builtin_amdgcn_mfma_f32_4x4x1f32(x0[k], y0[k], acc, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f32_4x4x1f32(x1[k], y1[k], acc2, 0, 0, 0);
+            }
+        };
+        using R0 = std::integral_constant<int, 0>;
+        using R1 = std::integral_constant<int, 1>;
+        using NOH = std::integral_constant<bool, false>;
+        using YH = std::integral_constant<bool, true>;
+        const int G0 = (cnt0 + 1) >> 1, G = G0 + ((cnt1 + 1) >> 1);
+        for (int g = 0; g < G - 1; ++g) {
+            if (g < G0)
+                grp(R0{}, NOH{}, 2 * g);
+            else
+                grp(R1{}, NOH{}, 2 * (g - G0));
+        }
+        if (G > 0) {
+            if (G - 1 < G0)
+                grp(R0{}, YH{}, 2 * (G - 1));
+            else
+                grp(R1{}, YH{}, 2 * (G - 1 - G0));
+        } else {
+            prefetch();
+        }
+        a0 += a0b;
+        a1 += a1b;
+        wave_sync_lds();  // the area takes the next column's lists
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            if (!C.val[i]) continue;
+            const f32x4 &acc = i ? a1 : a0;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const uint32_t e = C.off[i] + v * 9;
+                float o = (float)ep.alpha * acc[v];
+                if (Prev) o = fmaf((float)ep.beta, C.prev[i][v], o);
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, o), r_out, (int)(e * 4), 0, 0);
+                const double od = (double)o;
+                if constexpr (MAXACC > 0)
+                    if (ep.nacc > 0)
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, C.acc[i][v] + wq * od), r_acc,
+                                                              (int)(e * 8), 0, 0);
+                if (ep.hist) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, o), r_hist, (int)(e * 4), 0, 0);
+                if (row0 + i == jc && 3 * (slot / 3) + v == bcol) tr += od;
+            }
+        }
+    };
+    if (nj > 0) {
+        Set S0, S1;
+        int jj = wave;
+        lrec(jj, S0);
+        lrow(S0);
+        lrec(jj + NW, S1);
+        for (; jj < nj; jj += 2 * NW) {
+            column(S0, S1, jj);
+            if (jj + NW >= nj) break;
+            column(S1, S0, jj + NW);
+        }
+    }
+    if (ep.trace_partial) {
+        const double sm = bsum<NT>(tr);
+        if (threadIdx.x == 0) ep.trace_partial[tile] = sm;
+    }
+}
+
+template <int NW>
+hipError_t launch_lean9(const ListedPlanDev &plan, const ProductOperands &ops, const Epilogue &ep,
+                        hipStream_t st, size_t *lds_out) {
+    const size_t lds = lean9_lds<NW>(plan).total;
+    if (lds_out) {
+        *lds_out = lds;
+        return hipSuccess;
+    }
+    if (plan.ntiles == 0) return hipSuccess;
+    if (ep.nacc > 1) return launch_9<NW, 1, 4>(plan, ops, ep, st, lds_out);  // more sums: k_listed9
+    if (plan.entry_width != 1 || plan.cmax != 2 || !plan.off31) return hipErrorInvalidValue;
+    const void *fn = ep.nacc == 1 ? (const void *)k_lean9<NW, 1> : (const void *)k_lean9<NW, 0>;
+    static int raised_device = -1;
+    static size_t raised_to = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (lds > 65536 && (raised_device != dev || raised_to < lds)) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_lean9<NW, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_lean9<NW, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        raised_device = dev;
+        raised_to = lds;
+    }
+    (void)fn;
+    const int nt8 = (plan.ntiles + 7) & ~7;
+    if (ep.nacc == 1)
+        hipLaunchKernelGGL((k_lean9<NW, 1>), dim3(nt8), dim3(64 * NW), lds, st, plan, ops, ep);
+    else
+        hipLaunchKernelGGL((k_lean9<NW, 0>), dim3(nt8), dim3(64 * NW), lds, st, plan, ops, ep);
+    return hipGetLastError();
+}
+
 template <typename T, int B, int CMAX>
 struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
@@ -1235,7 +1513,10 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
     if constexpr (MODE == 0) {
         if (plan.variant == 0) return launch_v<T, B, CMAX, NW, MODE, EW, false>(plan, ops, ep, st, lds_out);
         if constexpr (std::is_same<T, float>::value && B == 9 && CMAX == 2) {
-            // 9 x 9 blocks on the matrix cores
+            // 9 x 9 blocks on the matrix cores; 3, 4: pipelined columns
+            // (k_lean9) with 8 or 4 waves
+            if (plan.variant == 3) return launch_lean9<8>(plan, ops, ep, st, lds_out);
+            if (plan.variant == 4) return launch_lean9<4>(plan, ops, ep, st, lds_out);
             if (plan.variant == 1 || plan.variant == 2) {
                 if (ep.nacc <= 1) {
                     if (plan.variant == 1) return launch_9<4, EW, 1>(plan, ops, ep, st, lds_out);
@@ -1345,13 +1626,14 @@ hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
 }
 
 int listed_product_variants(int dtype, int b, const ListedPlanDev &plan) {
-    if (b == 9 && dtype == 1 && plan.cmax == 2) return 3;  // VALU, MFMA with 4 or 8 waves
+    if (b == 9 && dtype == 1 && plan.cmax == 2) return 5;  // VALU, MFMA with 4 or 8 waves, pipelined MFMA
     if (b != 4 || plan.cmax != 4) return 1;
     return dtype == 0 ? LVariant<double, 4, 4>::COUNT : LVariant<float, 4, 4>::COUNT;
 }
 
 bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int v) {
-    if (b == 9 && dtype == 1 && plan.cmax == 2) return v >= 0 && v < 3;
+    if (b == 9 && dtype == 1 && plan.cmax == 2)
+        return v >= 0 && v < 5 && (v < 3 || (plan.off31 && plan.entry_width == 1));
     if (b != 4 || plan.cmax != 4) return v == 0;
     if (v >= 16 && !(dtype == 1 && plan.lean_rec && plan.entry_width == 1)) return false;
     return dtype == 0 ? LVariant<double, 4, 4>::ok(v) : LVariant<float, 4, 4>::ok(v);
