@@ -144,6 +144,34 @@ def trace_from_moments(c: np.ndarray, t: np.ndarray) -> float:
     return float(0.5 * c[0] * t[0] + np.dot(c[1:], t[1:c.shape[0]]))
 
 
+def energy_traces(t: np.ndarray, lo: float, hi: float) -> np.ndarray:
+    """Tr(T_k H') for k = 0 .. len(t) - 2 from the moments t_k = Tr T_k(H~).
+
+    Sec. "Fermi Operator Expansion" checks the width of the occupation with
+    the energy E = Tr(K H) (= Tr(K' H') in the orthogonal frame).  With
+    H~ = sigma (H' - tau I) (Eqs. 2-3), H' = H~/sigma + tau I, and
+    Tr(T_k H~) follows from the recursion 2 x T_k = T_{k+1} + T_{k-1}:
+    Tr(T_0 H~) = t_1 and Tr(T_k H~) = (t_{k+1} + t_{k-1}) / 2 for k >= 1.
+    The truncated recursion keeps every diagonal block (the diagonal is in
+    P_K), so these traces are exact for the truncated chain too."""
+    sigma, tau = scale_shift(lo, hi)
+    t = np.asarray(t, dtype=np.float64)
+    m = t.shape[0] - 1
+    g = np.empty(m)
+    g[0] = t[1]
+    g[1:] = 0.5 * (t[2:m + 1] + t[0:m - 1])
+    return g / sigma + tau * t[:m]
+
+
+def energy_from_moments(c: np.ndarray, t: np.ndarray, lo: float, hi: float) -> float:
+    """E = Tr(p(H') H') = c_0/2 Tr(T_0 H') + sum_j c_j Tr(T_j H') (Eq. 1);
+    needs one moment more than coefficients."""
+    e = energy_traces(t, lo, hi)
+    n = c.shape[0]
+    assert e.shape[0] >= n
+    return float(0.5 * c[0] * e[0] + np.dot(c[1:], e[1:n]))
+
+
 def electron_count(mu: float, t: np.ndarray, lo: float, hi: float, kT: float,
                    smearing: str = "erfc") -> float:
     """Tr K'(mu) in the orthogonal frame = N(mu), from the moments of H~'."""

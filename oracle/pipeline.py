@@ -130,21 +130,48 @@ def orthogonal_frame(H: BlockMat, S: BlockMat, pattern: BlockMat, s_bnds=None, n
 def fermi_operator(H: BlockMat, S: BlockMat, pattern: BlockMat, n_e: float, kT: float,
                    smearing: str = "erfc", s_bounds_=None, n_pl_s=None, h_bounds=None,
                    n_pl=None, mu=None, tol_fit: float = 1e-12, tol_fit_s: float = 1e-12,
-                   tol_ne: float | None = None):
-    """Steps 1-9.  Returns (K values [nnzb_K, b, b], info dict)."""
+                   tol_ne: float | None = None, adapt_kt: bool = False, kt_ratio: float = 1.25,
+                   tol_energy: float | None = None, max_kt_halvings: int = 4):
+    """Steps 1-9.  Returns (K values [nnzb_K, b, b], info dict).
+
+    adapt_kt: the width check of Sec. "Fermi Operator Expansion": after mu is
+    found for kT, a second occupation of width kT' = kt_ratio kT (its own mu
+    for the same N) gives E'; if |E - E'| > tol_energy the width is halved and
+    the expansion redone (a new degree unless n_pl is given), at most
+    max_kt_halvings times.  E and E' come from the moments of the same chain
+    (energy_from_moments), which runs one term longer for that."""
     X, Hp, sinfo = orthogonal_frame(H, S, pattern, s_bounds_, n_pl_s, tol_fit_s)
     K = pattern.pattern_csr()
     lo, hi = h_bounds if h_bounds is not None else cb.gershgorin(Hp.to_scipy())
     sigma, tau = cb.scale_shift(lo, hi)
     occ = cb.occ_erfc if smearing == "erfc" else cb.occ_fermi_dirac
-    if n_pl is None:
-        n_pl = cb.degree(lambda e: occ(e, tau, kT), lo, hi, tol_fit)
     Ht = scaled(Hp, lo, hi)
-    _, mom = chebyshev(Ht, K, n_pl, None)
-    it = 0
-    if mu is None:
-        tol_ne = 1e-8 * n_e if tol_ne is None else tol_ne
-        mu, it = cb.bisect_mu(mom, lo, hi, kT, n_e, tol_ne, smearing)
+    tol_ne = 1e-8 * n_e if tol_ne is None else tol_ne
+    tol_e = 1e-4 * n_e if tol_energy is None else tol_energy
+    n_pl_given = n_pl
+    halvings = 0
+    energy = energy_wide = float("nan")
+    while True:
+        n_pl = n_pl_given if n_pl_given is not None else cb.degree(lambda e: occ(e, tau, kT), lo, hi, tol_fit)
+        _, mom_e = chebyshev(Ht, K, n_pl + 1 if adapt_kt else n_pl, None)
+        mom = mom_e[:n_pl]
+        it = 0
+        mu_k = mu
+        if mu_k is None:
+            mu_k, it = cb.bisect_mu(mom, lo, hi, kT, n_e, tol_ne, smearing)
+        if not adapt_kt:
+            break
+        c = cb.cheb_coeffs(lambda e: occ(e, mu_k, kT), lo, hi, n_pl)
+        energy = cb.energy_from_moments(c, mom_e, lo, hi)
+        kT2 = kt_ratio * kT
+        mu2, _ = cb.bisect_mu(mom, lo, hi, kT2, n_e, tol_ne, smearing)
+        c2 = cb.cheb_coeffs(lambda e: occ(e, mu2, kT2), lo, hi, n_pl)
+        energy_wide = cb.energy_from_moments(c2, mom_e, lo, hi)
+        if abs(energy - energy_wide) <= tol_e or halvings >= max_kt_halvings:
+            break
+        kT *= 0.5
+        halvings += 1
+    mu = mu_k
     c = cb.cheb_coeffs(lambda e: occ(e, mu, kT), lo, hi, n_pl)
     acc, _ = chebyshev(Ht, K, n_pl, c[None, :])
     Kp = K.with_values(acc[0])
@@ -155,7 +182,8 @@ def fermi_operator(H: BlockMat, S: BlockMat, pattern: BlockMat, n_e: float, kT: 
     trKS = float(Kfin.to_scipy().multiply(Sc.to_scipy()).sum())
     info = dict(mu=mu, lo=lo, hi=hi, n_pl=n_pl, n_pl_s=sinfo["n_pl"], s_lo=sinfo["lo"],
                 s_hi=sinfo["hi"], moments=mom, bisect_iters=it, trKS=trKS,
-                ne_chain=cb.trace_from_moments(c, mom))
+                ne_chain=cb.trace_from_moments(c, mom), energy=energy,
+                energy_wide=energy_wide, kT=kT, kt_halvings=halvings)
     return pattern.to_block(Kv), info
 
 
