@@ -196,6 +196,9 @@ def main():
     ap.add_argument("--workload", default="large80k")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--width-check", action="store_true",
+                    help="also run one call with the occupation-width check (adapt_kt) and "
+                         "report E, E', the kT halvings and its time (outside the timed steps)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (HBM counter calibration)")
     ap.add_argument("--chain-only", type=int, default=0, metavar="N_PL",
@@ -334,6 +337,19 @@ def main():
                            time_to_solution_ms=round(ms_per_step, 2)),
                roofline=roof)
 
+    if args.width_check:
+        log("width check (adapt_kt)")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, winfo = run(dict(fast, adapt_kt=1))
+        torch.cuda.synchronize()
+        tw = (time.perf_counter() - t0) * 1e3
+        out["width_check"] = dict(ms=round(tw, 1), energy=winfo["energy"], energy_wide=winfo["energy_wide"],
+                                  kt_used=winfo["kt_used"], kt_halvings=winfo["kt_halvings"],
+                                  n_pl=winfo["n_pl"], passes=winfo["passes"],
+                                  tol_energy=1e-4 * sysm.n_electrons)
+        log(f"width check: {tw:.0f} ms E={winfo['energy']:.6f} E'={winfo['energy_wide']:.6f} "
+            f"halvings={winfo['kt_halvings']} kT={winfo['kt_used']}")
     if not args.no_plain:
         log("plain float64 form (Gershgorin bounds, two passes, same tol_fit)")
         # the chain reports its own progress; the stream waits it adds are

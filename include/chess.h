@@ -114,6 +114,16 @@ typedef struct {
     double mu_bracket[2];/* not NaN: search mu here first, fall back to the full bounds */
     double eig_width;    /* kT of the occupation used to extract eigenvalues (1e-3) */
     double bound_margin; /* relative margin added to Lanczos bounds (0.02) */
+    /* Width check of Sec. "Fermi Operator Expansion" (chess_fermi_operator):
+     * after mu is found for kT, E = Tr(K' H') is compared with E' for the
+     * wider occupation kt_ratio * kT (its own mu for the same N); both come
+     * from the moments of the same chain, which runs one term longer.  While
+     * |E - E'| > tol_energy, kT is halved and the expansion redone (a new
+     * degree unless n_pl is given), at most max_kt_halvings times. */
+    int32_t adapt_kt;        /* 1: check and adapt the width (default 0) */
+    int32_t max_kt_halvings; /* (4) */
+    double kt_ratio;         /* kT'/kT of the second occupation (> 1; default 1.25) */
+    double tol_energy;       /* |E - E'| threshold in Ha (<= 0: 1e-4 N_e) */
 } chess_opts;
 
 typedef struct {
@@ -138,6 +148,10 @@ typedef struct {
                                bit 1 = mu not inside the predicted bracket */
     double pred_lo, pred_hi, pred_mu; /* predictor outputs (NaN unless CHESS_BOUNDS_LEARNED) */
     double ms_learned;      /* features + inference time */
+    double energy;          /* adapt_kt: E = Tr(K' H') at the returned kT (NaN otherwise) */
+    double energy_wide;     /* adapt_kt: E' at kt_ratio times the returned kT */
+    double kt_used;         /* kT of the returned K */
+    int32_t kt_halvings;    /* adapt_kt: halvings of kT taken */
 } chess_info;
 
 /*

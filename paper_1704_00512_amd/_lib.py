@@ -42,7 +42,9 @@ class chess_opts(ctypes.Structure):
                 ("tol_ne", ctypes.c_double), ("bounds", ctypes.c_double * 2),
                 ("s_bounds", ctypes.c_double * 2), ("mu", ctypes.c_double),
                 ("mu_bracket", ctypes.c_double * 2), ("eig_width", ctypes.c_double),
-                ("bound_margin", ctypes.c_double)]
+                ("bound_margin", ctypes.c_double), ("adapt_kt", ctypes.c_int32),
+                ("max_kt_halvings", ctypes.c_int32), ("kt_ratio", ctypes.c_double),
+                ("tol_energy", ctypes.c_double)]
 
 
 class chess_info(ctypes.Structure):
@@ -58,7 +60,9 @@ class chess_info(ctypes.Structure):
                 ("ms_post", ctypes.c_double), ("ms_chain_kernel", ctypes.c_double),
                 ("kernel_variant", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("pred_lo", ctypes.c_double), ("pred_hi", ctypes.c_double),
-                ("pred_mu", ctypes.c_double), ("ms_learned", ctypes.c_double)]
+                ("pred_mu", ctypes.c_double), ("ms_learned", ctypes.c_double),
+                ("energy", ctypes.c_double), ("energy_wide", ctypes.c_double),
+                ("kt_used", ctypes.c_double), ("kt_halvings", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -1114,6 +1114,8 @@ static chess_opts resolve_opts(const chess_opts *o) {
     if (r.lanczos_steps <= 0) r.lanczos_steps = 40;
     if (!(r.eig_width > 0)) r.eig_width = 1e-3;
     if (!(r.bound_margin >= 0)) r.bound_margin = 0.02;
+    if (!(r.kt_ratio > 1)) r.kt_ratio = 1.25;
+    if (r.max_kt_halvings < 0) r.max_kt_halvings = 0;
     return r;
 }
 
@@ -1422,6 +1424,26 @@ static void fill_info_defaults(chess_info *info) {
     info->kernel_variant = -1;
 }
 
+// E = Tr(p(H') H') from the moments t_k = Tr T_k(H~), one more than the
+// coefficients c (Sec. "Fermi Operator Expansion" compares E for two widths).
+// H' = H~ / sigma + tau I, and the recursion 2 x T_k = T_{k+1} + T_{k-1} gives
+// Tr(T_0 H~) = t_1, Tr(T_k H~) = (t_{k+1} + t_{k-1}) / 2; the truncated chain
+// keeps every diagonal block, so this holds for it exactly.
+static double energy_from_moments(const std::vector<double> &c, const std::vector<double> &t, double lo,
+                                  double hi) {
+    double sigma, tau;
+    hostmath::scale_shift(lo, hi, &sigma, &tau);
+    const int n = (int)c.size();
+    if ((int)t.size() < n + 1) CHESS_THROW(CHESS_E_ARG, "energy needs %d moments", n + 1);
+    auto tr = [&](int k) {
+        const double g = k == 0 ? t[1] : 0.5 * (t[k + 1] + t[k - 1]);
+        return g / sigma + tau * t[k];
+    };
+    double e = 0.5 * c[0] * tr(0);
+    for (int k = 1; k < n; ++k) e += c[k] * tr(k);
+    return e;
+}
+
 static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_matrix *S,
                            const chess_pattern *pattern, double n_e, double kT,
                            chess_matrix *K_out, chess_info *info, const chess_opts *opts) {
@@ -1496,6 +1518,14 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     int variant = -1;
     bool have_hist = false;
     Timer tm(st);
+    // Width check of Sec. "Fermi Operator Expansion" (adapt_kt): the chain
+    // runs one term longer so that E = Tr(K' H') follows from its moments;
+    // E at kT and E' at kt_ratio kT (each with its own mu) are compared and
+    // kT is halved (a new expansion) while they differ by more than tol_energy.
+    const int extra = o.adapt_kt ? 1 : 0;
+    double energy = nan, energy_wide = nan, ms_mu = 0.0, mu = o.mu;
+    int halvings = 0, iters = 0;
+    for (;;) {
     for (int attempt = 0;; ++attempt) {
         double sigma, tau;
         hostmath::scale_shift(lo, hi, &sigma, &tau);
@@ -1509,7 +1539,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         if (o.store_history && !std::isfinite(o.mu)) {
             size_t freeb = 0, totalb = 0;
             HIPCHECK(hipMemGetInfo(&freeb, &totalb));
-            const size_t need = vbytes(PK, dtype) * (size_t)n_pl;
+            const size_t need = vbytes(PK, dtype) * (size_t)(n_pl + extra);
             if (need + ((size_t)1 << 30) < freeb) {
                 try {
                     hist.alloc(need);
@@ -1525,13 +1555,14 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         rq.PM = PH;
         rq.Mt = Ht.as<double>();
         rq.PK = PK;
-        rq.n_pl = n_pl;
+        rq.n_pl = n_pl + extra;
         rq.dtype = dtype;
         rq.moments = &mom;
         std::vector<double> c_fixed;
         if (std::isfinite(o.mu)) {
-            // mu given: one accumulating pass
+            // mu given: one accumulating pass (the extra term has weight 0)
             c_fixed = hostmath::cheb_coeffs(occupation(o.smearing, o.mu, kT), lo, hi, n_pl);
+            c_fixed.resize(n_pl + extra, 0.0);
             rq.nq = 1;
             rq.coef = c_fixed.data();
             rq.acc[0] = accK.as<double>();
@@ -1572,9 +1603,11 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         reexp++;
     }
     // mu search on the moments
+    const std::vector<double> mom_e(mom);  // with the extra moment
+    mom.resize(n_pl);
     const double t_mu0 = now_ms();
-    double mu = o.mu;
-    int iters = 0;
+    mu = o.mu;
+    iters = 0;
     hostmath::CountFunction N;
     N.init(mom, lo, hi, kT, o.smearing == CHESS_ERFC ? 0 : 1);
     if (!std::isfinite(mu)) {
@@ -1591,7 +1624,29 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         }
         if (!found) CHESS_THROW(CHESS_E_NOCONV, "N(mu) does not bracket %g electrons", n_e);
     }
-    const double ms_mu = now_ms() - t_mu0;
+    ms_mu += now_ms() - t_mu0;
+    if (!o.adapt_kt) break;
+    {
+        const std::vector<double> c1 = hostmath::cheb_coeffs(occupation(o.smearing, mu, kT), lo, hi, n_pl);
+        energy = energy_from_moments(c1, mom_e, lo, hi);
+        const double kt2 = o.kt_ratio * kT;
+        hostmath::CountFunction N2;
+        N2.init(mom, lo, hi, kt2, o.smearing == CHESS_ERFC ? 0 : 1);
+        double mu2 = 0.0;
+        int it2 = 0;
+        const double tol_ne = o.tol_ne > 0 ? o.tol_ne : 1e-8 * n_e;
+        if (!hostmath::bisect_mu(N2, n_e, tol_ne, lo - 20 * kt2, hi + 20 * kt2, &mu2, &it2))
+            CHESS_THROW(CHESS_E_NOCONV, "N(mu) at the second width does not bracket %g electrons", n_e);
+        const std::vector<double> c2 = hostmath::cheb_coeffs(occupation(o.smearing, mu2, kt2), lo, hi, n_pl);
+        energy_wide = energy_from_moments(c2, mom_e, lo, hi);
+        const double tol_e = o.tol_energy > 0 ? o.tol_energy : 1e-4 * n_e;
+        if (std::fabs(energy - energy_wide) <= tol_e || halvings >= o.max_kt_halvings) break;
+        kT *= 0.5;
+        halvings++;
+        // a bracket predicted for the first width does not hold for the next
+        if (!br_given) br[0] = br[1] = nan;
+    }
+    }
     const std::vector<double> c = hostmath::cheb_coeffs(occupation(o.smearing, mu, kT), lo, hi, n_pl);
     double ne_chain = 0.5 * c[0] * mom[0];
     for (int j = 1; j < n_pl; ++j) ne_chain += c[j] * mom[j];
@@ -1656,6 +1711,10 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         info->pred_mu = pred[2];
         info->fallback = fallback;
         info->ms_learned = ms_learned;
+        info->energy = energy;
+        info->energy_wide = energy_wide;
+        info->kt_used = kT;
+        info->kt_halvings = halvings;
     }
 }
 
@@ -2301,6 +2360,10 @@ void chess_default_opts(chess_opts *o) {
     o->mu_bracket[0] = o->mu_bracket[1] = nan;
     o->eig_width = 1e-3;
     o->bound_margin = 0.02;
+    o->adapt_kt = 0;
+    o->max_kt_halvings = 4;
+    o->kt_ratio = 1.25;
+    o->tol_energy = 0;
 }
 
 int chess_create(chess_ctx **out, int device, void *stream) {
