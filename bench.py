@@ -196,6 +196,10 @@ def main():
     ap.add_argument("--workload", default="large80k")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="also time a warm-started call (S^-1/2, bounds and a mu bracket from the "
+                         "previous call) and the inverse of S from default bounds [0.5, 1] "
+                         "against adjusted ones (outside the timed steps)")
     ap.add_argument("--width-check", action="store_true",
                     help="also run one call with the occupation-width check (adapt_kt) and "
                          "report E, E', the kT halvings and its time (outside the timed steps)")
@@ -251,7 +255,7 @@ def main():
             log(f"copy {i}: {n * 4} bytes")
         return
 
-    from paper_1704_00512_amd import BlockPattern, Context, chess_fermi_operator
+    from paper_1704_00512_amd import BlockPattern, Context, chess_fermi_operator, chess_matrix_power
     from workloads.generator import CONFIGS, make_config
 
     log(f"generating workload {args.workload} {CONFIGS[args.workload]}")
@@ -337,6 +341,43 @@ def main():
                            time_to_solution_ms=round(ms_per_step, 2)),
                roofline=roof)
 
+    if args.warm_start:
+        log("warm start")
+        X = pk.zeros()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, c_info = run(dict(fast, sinvhalf_out=X))
+        torch.cuda.synchronize()
+        t_cold = (time.perf_counter() - t0) * 1e3
+        mu0 = c_info["mu"]
+        t0 = time.perf_counter()
+        _, w_info = run(dict(fast, sinvhalf_in=X, bounds=(c_info["lo"], c_info["hi"]),
+                             mu_bracket=(mu0 - 0.01, mu0 + 0.01)))
+        torch.cuda.synchronize()
+        t_warm = (time.perf_counter() - t0) * 1e3
+        del X
+        out["warm_start"] = dict(cold_ms=round(t_cold, 1), warm_ms=round(t_warm, 1),
+                                 cold_bisect_iters=c_info["bisect_iters"],
+                                 warm_bisect_iters=w_info["bisect_iters"],
+                                 cold_ms_setup=round(c_info["ms_setup"] + c_info["ms_s_chain"], 1),
+                                 warm_ms_setup=round(w_info["ms_setup"] + w_info["ms_s_chain"], 1),
+                                 mu_diff=abs(w_info["mu"] - mu0))
+        log(f"warm start: cold {t_cold:.0f} ms, warm {t_warm:.0f} ms")
+        # the inverse of S from default bounds (the paper's Fig. 9 setup) and
+        # from the bounds that search ends with
+        Sinv = pk.zeros()
+        res = {}
+        for name, kw in (("default", dict(s_bounds=(0.5, 1.0), max_reexpand=60)), ("adjusted", None)):
+            if kw is None:
+                kw = dict(s_bounds=(res["default"]["lo"], res["default"]["hi"]))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, p_info = chess_matrix_power(ctx, S, ph, -1.0, pk, out=Sinv, precision="f32", tol_fit_s=1e-6, **kw)
+            torch.cuda.synchronize()
+            res[name] = dict(ms=round((time.perf_counter() - t0) * 1e3, 1), lo=p_info["lo"],
+                             hi=p_info["hi"], n_pl=p_info["n_pl"], reexpansions=p_info["reexpansions"])
+        out["inverse_bounds"] = res
+        log(f"inverse: default bounds {res['default']}, adjusted {res['adjusted']}")
     if args.width_check:
         log("width check (adapt_kt)")
         torch.cuda.synchronize()

@@ -124,6 +124,16 @@ typedef struct {
     int32_t max_kt_halvings; /* (4) */
     double kt_ratio;         /* kT'/kT of the second occupation (> 1; default 1.25) */
     double tol_energy;       /* |E - E'| threshold in Ha (<= 0: 1e-4 N_e) */
+    /* Warm start (chess_fermi_operator, chess_eigs_in_interval): in an SCF
+     * cycle S does not change, so S^-1/2 from an earlier call can be given
+     * back and the S chain is skipped (Sec. "Determination of the eigenvalue
+     * bounds and polynomial degree": guesses from the previous iteration;
+     * the bounds and a mu bracket go in bounds / mu_bracket).  Both are
+     * device arrays of float64 on `pattern` (nnzb * b * b values, blocks in
+     * pattern order, row-major), owned by the caller; NULL = not used.
+     * With CHESS_BOUNDS_LEARNED and sinvhalf_in, s_bounds must be given. */
+    const void *sinvhalf_in; /* S^-1/2 to use instead of computing it */
+    void *sinvhalf_out;      /* receives the S^-1/2 the call used */
 } chess_opts;
 
 typedef struct {
@@ -313,6 +323,9 @@ int chess_fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_matr
  * Matrix power S^a for any real a (Sec. "Matrix powers"): the same expansion
  * with f(x) = x^a over the spectral bounds of S; non-integer or negative a
  * need a positive lower bound (else CHESS_E_NOT_SPD).  Sa_out is on `pattern`.
+ * The bounds, degree and Eq. 7 threshold are those of S in opts: s_bounds,
+ * n_pl_s, tol_fit_s (bounds that fail the growth test |Tr T_k| <= 1.01 n
+ * are widened on both sides by 10 % of the width, up to max_reexpand times).
  */
 int chess_matrix_power(chess_ctx *ctx, const chess_matrix *S, double a,
                        const chess_pattern *pattern, chess_matrix *Sa_out,

@@ -44,7 +44,8 @@ class chess_opts(ctypes.Structure):
                 ("mu_bracket", ctypes.c_double * 2), ("eig_width", ctypes.c_double),
                 ("bound_margin", ctypes.c_double), ("adapt_kt", ctypes.c_int32),
                 ("max_kt_halvings", ctypes.c_int32), ("kt_ratio", ctypes.c_double),
-                ("tol_energy", ctypes.c_double)]
+                ("tol_energy", ctypes.c_double), ("sinvhalf_in", ctypes.c_void_p),
+                ("sinvhalf_out", ctypes.c_void_p)]
 
 
 class chess_info(ctypes.Structure):

@@ -62,6 +62,14 @@ def _mat(p: BlockPattern, val: torch.Tensor) -> _lib.chess_matrix:
     return _lib.chess_matrix(p.c(), val.data_ptr(), _lib.CHESS_F64)
 
 
+def _check_x(pattern: BlockPattern, opts: dict):
+    # a warm-start S^-1/2 lives on the kernel pattern
+    for k in ("sinvhalf_in", "sinvhalf_out"):
+        v = opts.get(k)
+        if v is not None and tuple(v.shape) != (pattern.nnzb, pattern.b, pattern.b):
+            raise ValueError(f"{k} shape {tuple(v.shape)} != {(pattern.nnzb, pattern.b, pattern.b)}")
+
+
 def default_opts(**kw) -> _lib.chess_opts:
     o = _lib.chess_opts()
     _lib.load().chess_default_opts(ctypes.byref(o))
@@ -77,6 +85,11 @@ def default_opts(**kw) -> _lib.chess_opts:
             o.precision = {"f64": _lib.CHESS_F64, "f32": _lib.CHESS_F32}[v]
         elif k == "smearing" and isinstance(v, str):
             o.smearing = {"erfc": _lib.CHESS_ERFC, "fermi_dirac": _lib.CHESS_FERMI_DIRAC}[v]
+        elif k in ("sinvhalf_in", "sinvhalf_out"):
+            # a float64 CUDA tensor on the kernel pattern, kept alive by the caller
+            if v is not None and (v.dtype != torch.float64 or not v.is_cuda or not v.is_contiguous()):
+                raise ValueError(f"{k} must be a contiguous float64 CUDA tensor")
+            setattr(o, k, None if v is None else v.data_ptr())
         elif k == "bounds_mode" and isinstance(v, str):
             o.bounds_mode = {"gershgorin": 0, "lanczos": 1, "learned": 2}[v]
         else:
@@ -133,6 +146,7 @@ def chess_fermi_operator(ctx: Context, H: torch.Tensor, pat_h: BlockPattern, S: 
                          kT: float, out: torch.Tensor | None = None, **opts):
     K = pattern.zeros() if out is None else out
     info = _lib.chess_info()
+    _check_x(pattern, opts)
     o = default_opts(**opts)
     mh, ms, mk, pk = _mat(pat_h, H), _mat(pat_s, S), _mat(pattern, K), pattern.c()
     ctx._check(ctx._L.chess_fermi_operator(ctx._h, ctypes.byref(mh), ctypes.byref(ms),
@@ -158,6 +172,7 @@ def chess_eigs_in_interval(ctx: Context, H: torch.Tensor, pat_h: BlockPattern, S
     buf = (ctypes.c_double * max(capacity, 1))()
     nf = ctypes.c_int64(0)
     info = _lib.chess_info()
+    _check_x(pattern, opts)
     o = default_opts(**opts)
     mh, ms, pk = _mat(pat_h, H), _mat(pat_s, S), pattern.c()
     rc = ctx._L.chess_eigs_in_interval(ctx._h, ctypes.byref(mh), ctypes.byref(ms), float(lo),

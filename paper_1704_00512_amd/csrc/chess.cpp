@@ -1238,11 +1238,19 @@ static void build_frame(chess_ctx *ctx, const Pattern *PH, const double *H, cons
     hipStream_t st = ctx->stream;
     Timer t(st);
     t.start();
-    double slo, shi;
-    s_bounds(ctx, PS, S, o, true, &slo, &shi);
-    F.accX.alloc(sizeof(double) * (size_t)PK->nnzb * PK->b * PK->b);
-    double *accs[1] = {F.accX.as<double>()};
-    F.s = power_chain(ctx, PS, S, PK, {-0.5}, o, o.n_pl_s, o.tol_fit_s, accs, slo, shi);
+    const size_t xbytes = sizeof(double) * (size_t)PK->nnzb * PK->b * PK->b;
+    F.accX.alloc(xbytes);
+    if (o.sinvhalf_in) {
+        // S^-1/2 from an earlier call (Sec. "Performance": in an SCF cycle S
+        // does not change): no S chain; its bounds are those given, if any
+        transpose_into(ctx, PK, (const double *)o.sinvhalf_in, F.accX.as<double>());
+        F.s = PowerResult{o.s_bounds[0], o.s_bounds[1], 0, 0, 0.0, -1};
+    } else {
+        double slo, shi;
+        s_bounds(ctx, PS, S, o, true, &slo, &shi);
+        double *accs[1] = {F.accX.as<double>()};
+        F.s = power_chain(ctx, PS, S, PK, {-0.5}, o, o.n_pl_s, o.tol_fit_s, accs, slo, shi);
+    }
     F.ms_s = t.stop();
     t.start();
     const EmbedMap *eh = get_embed(ctx, PH, PK, "H in the kernel pattern");
@@ -1258,6 +1266,7 @@ static void build_frame(chess_ctx *ctx, const Pattern *PH, const double *H, cons
     product(ctx, 0, get_plan(ctx, PK, PK, PH, 0), F.X.p, ZT.p, Hraw.p, Epilogue{});
     F.Hp.alloc(Hraw.bytes);
     HIPCHECK(launch_symmetrize(PH->b, PH->nnzb, PH->d_tmap.as<int64_t>(), Hraw.as<double>(), F.Hp.as<double>(), st));
+    if (o.sinvhalf_out) HIPCHECK(hipMemcpyAsync(o.sinvhalf_out, F.X.p, xbytes, hipMemcpyDeviceToDevice, st));
     F.ms_transform = t.stop();
 }
 
@@ -1486,6 +1495,8 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         // Gershgorin interval) and a predicted mu bracket; Eq. 6 and the
         // growth test still judge the bounds, bisection still judges mu
         const double t0 = now_ms();
+        if (!(std::isfinite(F.s.lo) && std::isfinite(F.s.hi)))
+            CHESS_THROW(CHESS_E_ARG, "learned bounds with a given S^-1/2 need s_bounds");
         compute_features(ctx, PH, F.Hp.as<double>(), PK, F.s.lo, F.s.hi, n_e, kT, fe);
         predict(ctx, fe, pred);
         const Model &M = ctx->model;
@@ -2364,6 +2375,8 @@ void chess_default_opts(chess_opts *o) {
     o->max_kt_halvings = 4;
     o->kt_ratio = 1.25;
     o->tol_energy = 0;
+    o->sinvhalf_in = nullptr;
+    o->sinvhalf_out = nullptr;
 }
 
 int chess_create(chess_ctx **out, int device, void *stream) {
