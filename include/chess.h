@@ -368,6 +368,37 @@ int chess_chebyshev(chess_ctx *ctx, const chess_matrix *M, double lo, double hi,
 int chess_masked_product(chess_ctx *ctx, const chess_matrix *A, const chess_matrix *B,
                          chess_matrix *C);
 
+/*
+ * Segment Storage Format (Sec. "Storage format of the sparse matrices"), for
+ * callers that hold matrices the way CheSS stores them.  Host arrays only, no
+ * context, no device work.  SSF: nseg segments of consecutive non-zero
+ * entries of an n x n matrix, keyg [nseg][4] = (c_s, c_e, r_s, r_e), 1-based,
+ * a segment running in row-major order from (r_s, c_s) to (r_e, c_e) (it may
+ * continue over a row end); segments sorted and not overlapping; values in
+ * one array of nval entries; keyv [nseg] (1-based) where each segment starts
+ * in it, or NULL for one after the other.
+ *
+ * chess_ssf_to_bcsr: block CSR of edge b (n a multiple of b): block (I, J)
+ * is stored when any entry inside it is; the others of a stored block are 0.
+ *   row_ptr [n/b + 1], col_idx [capacity], val_bcsr [capacity * b * b]
+ *   (row-major blocks in pattern order); all three NULL: only *nnzb_out is
+ *   set.  CHESS_E_CAPACITY when capacity < nnzb (then *nnzb_out holds it);
+ *   CHESS_E_ARG for segments out of range, unsorted, overlapping or reaching
+ *   past nval.
+ * chess_bcsr_to_ssf: one segment per maximal run of consecutive block columns
+ *   in every scalar row (nseg = b * runs), keyv filled, values in segment
+ *   order.  keyg [capacity][4], keyv [capacity], val [*nval_out]; all three
+ *   NULL: only *nseg_out and *nval_out are set.  CHESS_E_CAPACITY when
+ *   capacity < nseg; CHESS_E_ARG for a malformed pattern (row_ptr not
+ *   starting at 0 or decreasing, columns out of range or not increasing).
+ */
+int chess_ssf_to_bcsr(int32_t b, int64_t n, int64_t nseg, const int64_t *keyg, const int64_t *keyv,
+                      const double *val, int64_t nval, int64_t *row_ptr, int32_t *col_idx,
+                      double *val_bcsr, int64_t capacity, int64_t *nnzb_out);
+int chess_bcsr_to_ssf(int32_t b, int32_t nbrows, const int64_t *row_ptr, const int32_t *col_idx,
+                      const double *val_bcsr, int64_t *keyg, int64_t *keyv, double *val, int64_t capacity,
+                      int64_t *nseg_out, int64_t *nval_out);
+
 #ifdef __cplusplus
 }
 #endif

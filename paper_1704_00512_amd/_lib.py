@@ -84,7 +84,8 @@ EXPORTS = ["chess_default_opts", "chess_create", "chess_destroy", "chess_last_er
            "chess_fermi_operator", "chess_matrix_power", "chess_eigs_in_interval",
            "chess_chebyshev", "chess_masked_product", "chess_set_progress",
            "chess_features", "chess_mlp_forward", "chess_mlp_grad", "chess_mlp_adam",
-           "chess_model_load", "chess_model_save", "chess_fermi_operator_batched"]
+           "chess_model_load", "chess_model_save", "chess_fermi_operator_batched",
+           "chess_ssf_to_bcsr", "chess_bcsr_to_ssf"]
 
 N_FEATURES, MLP_HIDDEN, MLP_OUT = 64, 128, 3
 MLP_PARAMS = MLP_HIDDEN * N_FEATURES + MLP_HIDDEN + MLP_OUT * MLP_HIDDEN + MLP_OUT
@@ -141,6 +142,9 @@ def load():
                                                P(chess_opts)]
     L.chess_model_load.argtypes = [vp, fp, ctypes.c_int64]
     L.chess_model_save.argtypes = [vp, fp, ctypes.c_int64]
+    i64, i32 = ctypes.c_int64, ctypes.c_int32
+    L.chess_ssf_to_bcsr.argtypes = [i32, i64, i64, vp, vp, vp, i64, vp, vp, vp, i64, P(i64)]
+    L.chess_bcsr_to_ssf.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i64, P(i64), P(i64)]
     for name in EXPORTS:
         if name not in ("chess_default_opts", "chess_last_error"):
             getattr(L, name).restype = ctypes.c_int

@@ -343,3 +343,56 @@ def chess_fermi_operator_batched(ctx: Context, systems, want_k=(True, True, True
         res["info"] = info.as_dict()
         result.append(res)
     return result
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def chess_ssf_to_bcsr(b: int, n: int, keyg, val, keyv=None):
+    """Segment Storage Format -> block CSR (host numpy arrays, see chess.h):
+    keyg [nseg, 4] (c_s, c_e, r_s, r_e, 1-based), val (1-D), keyv (1-based
+    starts or None).  Returns (row_ptr int64, col_idx int32, values [nnzb, b, b])."""
+    L = _lib.load()
+    keyg = np.ascontiguousarray(np.asarray(keyg, dtype=np.int64).reshape(-1, 4))
+    val = np.ascontiguousarray(np.asarray(val, dtype=np.float64).ravel())
+    kv = None if keyv is None else np.ascontiguousarray(np.asarray(keyv, dtype=np.int64))
+    if kv is not None and kv.size != keyg.shape[0]:
+        raise ValueError("keyv needs one entry per segment")
+    nnzb = ctypes.c_int64(0)
+    args = (int(b), int(n), keyg.shape[0], _ptr(keyg), _ptr(kv), _ptr(val), val.size)
+    rc = L.chess_ssf_to_bcsr(*args, None, None, None, 0, ctypes.byref(nnzb))
+    if rc != 0:
+        raise ChessError(rc, "chess_ssf_to_bcsr: malformed segments")
+    rp = np.zeros(n // b + 1, dtype=np.int64)
+    ci = np.zeros(max(nnzb.value, 1), dtype=np.int32)
+    vb = np.zeros((max(nnzb.value, 1), b, b), dtype=np.float64)
+    rc = L.chess_ssf_to_bcsr(*args, _ptr(rp), _ptr(ci), _ptr(vb), nnzb.value, ctypes.byref(nnzb))
+    if rc != 0:
+        raise ChessError(rc, "chess_ssf_to_bcsr failed")
+    return rp, ci[:nnzb.value], vb[:nnzb.value]
+
+
+def chess_bcsr_to_ssf(b: int, row_ptr, col_idx, val):
+    """Block CSR -> Segment Storage Format (host numpy arrays, see chess.h).
+    Returns (keyg [nseg, 4], keyv [nseg], values)."""
+    L = _lib.load()
+    rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    ci = np.ascontiguousarray(np.asarray(col_idx, dtype=np.int32))
+    vb = np.ascontiguousarray(np.asarray(val, dtype=np.float64))
+    nb = rp.size - 1
+    if vb.size != ci.size * b * b:
+        raise ValueError("values must be [nnzb, b, b]")
+    nseg, nval = ctypes.c_int64(0), ctypes.c_int64(0)
+    head = (int(b), nb, _ptr(rp), _ptr(ci), _ptr(vb))
+    rc = L.chess_bcsr_to_ssf(*head, None, None, None, 0, ctypes.byref(nseg), ctypes.byref(nval))
+    if rc != 0:
+        raise ChessError(rc, "chess_bcsr_to_ssf: malformed pattern")
+    kg = np.zeros((max(nseg.value, 1), 4), dtype=np.int64)
+    kv = np.zeros(max(nseg.value, 1), dtype=np.int64)
+    v = np.zeros(max(nval.value, 1), dtype=np.float64)
+    rc = L.chess_bcsr_to_ssf(*head, _ptr(kg), _ptr(kv), _ptr(v), nseg.value, ctypes.byref(nseg),
+                             ctypes.byref(nval))
+    if rc != 0:
+        raise ChessError(rc, "chess_bcsr_to_ssf failed")
+    return kg[:nseg.value], kv[:nseg.value], v[:nval.value]

@@ -6,7 +6,7 @@ import subprocess
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _CSRC = os.path.join(_HERE, "csrc")
-SOURCES = ["kernels.hip", "kernels_listed.hip", "learned.hip", "chess.cpp", "hostmath.cpp"]
+SOURCES = ["kernels.hip", "kernels_listed.hip", "learned.hip", "chess.cpp", "hostmath.cpp", "ssf.cpp"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere in the device code
