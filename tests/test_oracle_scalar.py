@@ -139,7 +139,7 @@ def test_eigenvalues_from_moments_on_designed_spectrum():
     # Eigenvalues spaced far apart compared to the occupation width are found
     # to within a small fraction of that width.
     lam = np.linspace(-0.8, 0.8, 33)
-    width = 2e-3
+    width = 8e-3  # spacing 0.05: still many widths apart, at a quarter of the degree
     lo, hi = -1.0, 1.0
     n_pl = cb.degree(lambda e: cb.occ_erfc(e, 0.0, width), lo, hi, 1e-10, m_max=6000)
     t = diag_moments(lam, n_pl)
