@@ -213,8 +213,8 @@ def main():
                     help="--chain-only: force this chain-kernel variant (CHESS_LISTED_VARIANT)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the multi-GPU column-slab sharding is a design "
-              "(see DESIGN.md), not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU only: the multi-GPU column-slab sharding is "
+              "described but not implemented", file=sys.stderr)
         sys.exit(2)
 
     log("importing torch")
