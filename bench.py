@@ -200,6 +200,8 @@ def main():
                     help="also time a warm-started call (S^-1/2, bounds and a mu bracket from the "
                          "previous call) and the inverse of S from default bounds [0.5, 1] "
                          "against adjusted ones (outside the timed steps)")
+    ap.add_argument("--tol-energy", type=float, default=0.0,
+                    help="--width-check: |E - E'| threshold in Ha (0: the library default, 1e-4 N_e)")
     ap.add_argument("--width-check", action="store_true",
                     help="also run one call with the occupation-width check (adapt_kt) and "
                          "report E, E', the kT halvings and its time (outside the timed steps)")
@@ -382,13 +384,13 @@ def main():
         log("width check (adapt_kt)")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, winfo = run(dict(fast, adapt_kt=1))
+        _, winfo = run(dict(fast, adapt_kt=1, tol_energy=args.tol_energy))
         torch.cuda.synchronize()
         tw = (time.perf_counter() - t0) * 1e3
         out["width_check"] = dict(ms=round(tw, 1), energy=winfo["energy"], energy_wide=winfo["energy_wide"],
                                   kt_used=winfo["kt_used"], kt_halvings=winfo["kt_halvings"],
                                   n_pl=winfo["n_pl"], passes=winfo["passes"],
-                                  tol_energy=1e-4 * sysm.n_electrons)
+                                  tol_energy=args.tol_energy if args.tol_energy > 0 else 1e-4 * sysm.n_electrons)
         log(f"width check: {tw:.0f} ms E={winfo['energy']:.6f} E'={winfo['energy_wide']:.6f} "
             f"halvings={winfo['kt_halvings']} kT={winfo['kt_used']}")
     if not args.no_plain:
