@@ -122,3 +122,25 @@ def test_batched_rejected_bounds_fall_back_to_gershgorin(gpu_ctx):
                                    h_bounds=(inf["lo"], inf["hi"]), n_pl=120,
                                    mu=a["mu_trial"][1])
         assert np.max(np.abs(r["K"][1].cpu().numpy() - Ko)) < 1e-10
+
+
+@pytest.mark.parametrize("variant,which", [(20, (0, 2, 4)), (21, (0, 2, 4)), (3, (1, 3))])
+def test_batched_forced_kernel_variants(gpu_ctx, monkeypatch, variant, which):
+    # the free-slot b = 4 kernels (20, 21) and the pipelined 9 x 9 one (3; with
+    # three sums it runs k_listed9) on block-diagonal batches: tiles never
+    # straddle systems and each tile weights its sums with its own system's
+    # coefficients
+    monkeypatch.setenv("CHESS_LISTED_VARIANT", str(variant))
+    ss = [systems()[i] for i in which]
+    args = batch_args(ss)
+    res = chess_fermi_operator_batched(gpu_ctx, args, precision="f32", bounds_mode="lanczos")
+    for s, a, r in zip(ss, args, res):
+        inf = r["info"]
+        assert inf["kernel_variant"] == variant
+        H, S, P = bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k)
+        for q in range(3):
+            Ko, _ = opl.fermi_operator(H, S, P, s.n_electrons, s.kT,
+                                       s_bounds_=(inf["s_lo"], inf["s_hi"]), n_pl_s=inf["n_pl_s"],
+                                       h_bounds=(inf["lo"], inf["hi"]), n_pl=inf["n_pl"],
+                                       mu=a["mu_trial"][q])
+            assert np.max(np.abs(r["K"][q].cpu().numpy() - Ko)) < 1e-5, (variant, s.n, q)
