@@ -831,12 +831,17 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
     // operands from global memory behind a scheduling barrier); b = 4 float64,
     // operands from global memory with 8 waves; b = 9 float32, the MFMA kernel
     // with pipelined columns and 8 waves (or without); variant 0 otherwise
+    auto fits = [&](int v) {
+        ListedPlanDev d = lp->dev;
+        d.variant = v;
+        return listed_product_variant_ok(dtype, b, d, v) && listed_product_lds_bytes(dtype, b, d) <= 160 * 1024;
+    };
     if (nvar == 1)
         lp->dev.variant = 0;
     else if (b == 4 && dtype == 1)
-        lp->dev.variant = listed_product_variant_ok(dtype, b, lp->dev, 20) ? 20 : 8;
+        lp->dev.variant = fits(20) ? 20 : 8;
     else if (b == 9)
-        lp->dev.variant = listed_product_variant_ok(dtype, b, lp->dev, 3) ? 3 : 2;
+        lp->dev.variant = fits(3) ? 3 : 2;
     else
         lp->dev.variant = 2;
     if (nvar == 1 || n_pl < 64) return;  // too short a chain to time variants on
