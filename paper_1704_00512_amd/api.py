@@ -46,6 +46,13 @@ class BlockPattern:
         return BlockPattern(b=int(b), nb=int(rp.shape[0] - 1), row_ptr=rp, col_idx=ci)
 
     def c(self) -> _lib.chess_pattern:
+        rp, ci = self.row_ptr, self.col_idx
+        if rp.dtype != torch.int64 or ci.dtype != torch.int32:
+            raise ValueError("pattern row_ptr must be int64 and col_idx int32")
+        if not (rp.is_cuda and ci.is_cuda and rp.is_contiguous() and ci.is_contiguous()):
+            raise ValueError("pattern row_ptr / col_idx must be contiguous CUDA tensors")
+        if rp.dim() != 1 or ci.dim() != 1 or rp.shape[0] != self.nb + 1:
+            raise ValueError(f"pattern row_ptr shape {tuple(rp.shape)} != ({self.nb + 1},)")
         return _lib.chess_pattern(self.b, self.nb, self.nnzb, self.row_ptr.data_ptr(),
                                   self.col_idx.data_ptr())
 

@@ -92,3 +92,15 @@ def test_product_path_imports_no_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.replace("Oracle", ""), f
+
+
+def test_pattern_index_types_are_checked_before_the_call():
+    # a pattern with the wrong index types or sizes never reaches the library
+    import torch
+    from paper_1704_00512_amd import BlockPattern
+    rp = torch.tensor([0, 1, 2], dtype=torch.int32)
+    ci = torch.tensor([0, 1], dtype=torch.int32)
+    with pytest.raises(ValueError, match="int64"):
+        BlockPattern(b=4, nb=2, row_ptr=rp, col_idx=ci).c()
+    with pytest.raises(ValueError, match="CUDA"):
+        BlockPattern(b=4, nb=2, row_ptr=rp.long(), col_idx=ci).c()
