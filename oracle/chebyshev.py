@@ -229,6 +229,23 @@ def eigenvalues_from_moments(t: np.ndarray, lo: float, hi: float, kT: float,
     return np.asarray(out)
 
 
+def homo_lumo_from_moments(t: np.ndarray, lo: float, hi: float, kT: float, n_e: float,
+                           smearing: str = "erfc", tol_n: float | None = None) -> tuple[float, float]:
+    """Sec. "Extraction of selected eigenvalues" (reading R19): the moments of
+    a density-kernel chain give rough HOMO and LUMO estimates.  With
+    N_h = ceil(N_e) occupied states, eigenvalue N_h solves N(e) = N_h - 1/2
+    and eigenvalue N_h + 1 solves N(e) = N_h + 1/2, at the chain's own width
+    kT, bisected on [lo - 20 kT, hi + 20 kT].  NaN where the index is outside
+    1..n (n = t_0 = Tr T_0)."""
+    n = int(round(t[0]))
+    nh = math.ceil(n_e - 1e-9)
+    tol = 1e-10 * max(1.0, n_e) if tol_n is None else tol_n
+    a, b = lo - 20 * kT, hi + 20 * kT
+    homo = bisect_mu(t, lo, hi, kT, nh - 0.5, tol, smearing, a, b)[0] if nh >= 1 else math.nan
+    lumo = bisect_mu(t, lo, hi, kT, nh + 0.5, tol, smearing, a, b)[0] if nh + 1 <= n else math.nan
+    return homo, lumo
+
+
 # ----------------------------------------------------------------------------
 # spectral bounds (the plain estimates the method starts from)
 # ----------------------------------------------------------------------------

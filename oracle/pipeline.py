@@ -172,6 +172,7 @@ def fermi_operator(H: BlockMat, S: BlockMat, pattern: BlockMat, n_e: float, kT: 
         kT *= 0.5
         halvings += 1
     mu = mu_k
+    homo, lumo = cb.homo_lumo_from_moments(mom, lo, hi, kT, n_e, smearing)
     c = cb.cheb_coeffs(lambda e: occ(e, mu, kT), lo, hi, n_pl)
     acc, _ = chebyshev(Ht, K, n_pl, c[None, :])
     Kp = K.with_values(acc[0])
@@ -183,7 +184,7 @@ def fermi_operator(H: BlockMat, S: BlockMat, pattern: BlockMat, n_e: float, kT: 
     info = dict(mu=mu, lo=lo, hi=hi, n_pl=n_pl, n_pl_s=sinfo["n_pl"], s_lo=sinfo["lo"],
                 s_hi=sinfo["hi"], moments=mom, bisect_iters=it, trKS=trKS,
                 ne_chain=cb.trace_from_moments(c, mom), energy=energy,
-                energy_wide=energy_wide, kT=kT, kt_halvings=halvings)
+                energy_wide=energy_wide, kT=kT, kt_halvings=halvings, homo=homo, lumo=lumo)
     return pattern.to_block(Kv), info
 
 

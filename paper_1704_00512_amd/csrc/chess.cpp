@@ -1435,6 +1435,7 @@ static void fill_info_defaults(chess_info *info) {
     info->mu = info->lo = info->hi = info->s_lo = info->s_hi = nan;
     info->tr_ks = info->ne_chain = info->penalty = nan;
     info->pred_lo = info->pred_hi = info->pred_mu = nan;
+    info->energy = info->energy_wide = info->homo = info->lumo = nan;
     info->kernel_variant = -1;
 }
 
@@ -1663,6 +1664,20 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         if (!br_given) br[0] = br[1] = nan;
     }
     }
+    // HOMO / LUMO estimates from the same moments (Sec. "Extraction of
+    // selected eigenvalues"): eigenvalue N solves N(e) = N - 1/2
+    double homo = nan, lumo = nan;
+    {
+        hostmath::CountFunction Ng;
+        Ng.init(mom, lo, hi, kT, o.smearing == CHESS_ERFC ? 0 : 1);
+        const double nh = std::ceil(n_e - 1e-9);
+        const double tol_g = 1e-10 * std::max(1.0, n_e);
+        int itg = 0;
+        if (nh >= 1 && !hostmath::bisect_mu(Ng, nh - 0.5, tol_g, lo - 20 * kT, hi + 20 * kT, &homo, &itg))
+            homo = nan;
+        if (nh + 1 <= (double)n && !hostmath::bisect_mu(Ng, nh + 0.5, tol_g, lo - 20 * kT, hi + 20 * kT, &lumo, &itg))
+            lumo = nan;
+    }
     const std::vector<double> c = hostmath::cheb_coeffs(occupation(o.smearing, mu, kT), lo, hi, n_pl);
     double ne_chain = 0.5 * c[0] * mom[0];
     for (int j = 1; j < n_pl; ++j) ne_chain += c[j] * mom[j];
@@ -1731,6 +1746,8 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         info->energy_wide = energy_wide;
         info->kt_used = kT;
         info->kt_halvings = halvings;
+        info->homo = homo;
+        info->lumo = lumo;
     }
 }
 

@@ -11,6 +11,7 @@ Decisions are tested only where the oracle's |E - E'| is at least 1.5x away
 from the threshold on either side."""
 import numpy as np
 import pytest
+import scipy.linalg
 import torch
 
 from oracle import chebyshev as cb
@@ -116,3 +117,45 @@ def test_halvings_match_oracle(gpu_ctx):
     # the cap on halvings is honoured
     _, info1 = run_gpu(gpu_ctx, s, 0.16, "f64", tol_energy=tol_e, max_kt_halvings=1)
     assert info1["kt_halvings"] == 1 and info1["kt_used"] == pytest.approx(0.08)
+
+
+def test_homo_lumo_match_oracle(gpu_ctx):
+    # the same moments on both sides at fixed bounds and degree; each side
+    # bisects to |N - target| <= 1e-10 N_e, about 1e-10 Ha here
+    s = system(0.02)
+    _, info = chess_fermi_operator(gpu_ctx, dv(s.H), gpat(s.pat_h), dv(s.S), gpat(s.pat_h),
+                                   gpat(s.pat_k), s.n_electrons, 0.02, precision="f64",
+                                   tol_ne=1e-10, **FIXED)
+    _, oinfo = opl.fermi_operator(bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k), s.n_electrons,
+                                  0.02, s_bounds_=FIXED["s_bounds"], n_pl_s=FIXED["n_pl_s"],
+                                  h_bounds=FIXED["bounds"], n_pl=FIXED["n_pl"], tol_ne=1e-10)
+    assert abs(info["homo"] - oinfo["homo"]) < 1e-8
+    assert abs(info["lumo"] - oinfo["lumo"]) < 1e-8
+    # N(homo) = N_e - 1/2 < N(mu) = N_e < N(lumo) = N_e + 1/2 and N is increasing
+    assert info["homo"] < info["mu"] < info["lumo"]
+
+
+def sym_blocks(rng, b, centre, spread):
+    G = rng.standard_normal((1, b, b))
+    return centre * np.eye(b)[None] + spread * 0.5 * (G + np.transpose(G, (0, 2, 1)))
+
+
+@pytest.mark.parametrize("b,seed,n_e", [(4, 51, 2.0), (9, 52, 4.5)])
+def test_homo_lumo_of_isolated_levels_are_the_eigenvalues(gpu_ctx, b, seed, n_e):
+    # one atom: levels at least 27 kT apart, so N(e) crosses N - 1/2 exactly at
+    # eigenvalue N up to the polynomial error (tol_fit 1e-12); default bounds
+    rng = np.random.default_rng(seed)
+    H, S = sym_blocks(rng, b, -0.5, 0.2), sym_blocks(rng, b, 1.0, 0.05)
+    e = scipy.linalg.eigh(H[0], S[0], eigvals_only=True)
+    kT = 2e-3
+    assert np.diff(e).min() > 25 * kT
+    p = g.pattern_from_pairs(1, b, np.array([0]), np.array([0]))
+    _, info = chess_fermi_operator(gpu_ctx, dv(H), gpat(p), dv(S), gpat(p), gpat(p), n_e, kT,
+                                   precision="f64", tol_fit=1e-12, tol_fit_s=1e-12)
+    nh = int(np.ceil(n_e))
+    assert abs(info["homo"] - e[nh - 1]) < 1e-8
+    assert abs(info["lumo"] - e[nh]) < 1e-8
+    # past the ends of the spectrum
+    _, full = chess_fermi_operator(gpu_ctx, dv(H), gpat(p), dv(S), gpat(p), gpat(p), float(b) - 0.5,
+                                   kT, precision="f64", tol_fit=1e-12, tol_fit_s=1e-12)
+    assert abs(full["homo"] - e[-1]) < 1e-8 and np.isnan(full["lumo"])

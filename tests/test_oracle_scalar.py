@@ -177,3 +177,22 @@ def test_lanczos_with_full_basis_is_exact():
     w = np.linalg.eigvalsh(A)
     tmin, tmax, rmin, rmax = cb.lanczos_extremes(lambda x: A @ x, 25, 25)
     assert abs(tmin - w[0]) < 1e-10 and abs(tmax - w[-1]) < 1e-10
+
+
+def test_homo_lumo_on_designed_spectrum():
+    # Levels 0.05 apart (over 6 widths): eigenvalues N_h = ceil(N_e) and
+    # N_h + 1 come out to a small fraction of the width; past either end of
+    # the spectrum the estimate is NaN.
+    lam = np.linspace(-0.8, 0.8, 33)
+    kT = 8e-3
+    lo, hi = -1.0, 1.0
+    n_pl = cb.degree(lambda e: cb.occ_erfc(e, 0.0, kT), lo, hi, 1e-10, m_max=6000)
+    t = diag_moments(lam, n_pl)
+    for n_e, nh in ((12, 12), (11.3, 12), (12.0000000001, 12), (1, 1), (32, 32)):
+        homo, lumo = cb.homo_lumo_from_moments(t, lo, hi, kT, n_e)
+        assert abs(homo - lam[nh - 1]) < 1e-3 * kT, (n_e, homo)
+        assert abs(lumo - lam[nh]) < 1e-3 * kT, (n_e, lumo)
+    homo, lumo = cb.homo_lumo_from_moments(t, lo, hi, kT, 33)
+    assert abs(homo - lam[32]) < 1e-3 * kT and math.isnan(lumo)
+    homo, lumo = cb.homo_lumo_from_moments(t, lo, hi, kT, 0)
+    assert math.isnan(homo) and abs(lumo - lam[0]) < 1e-3 * kT
