@@ -110,8 +110,28 @@ def cpu_baseline(sysm, budget_s=20.0):
                    k_stop=nprod + 2)
     dt = time.perf_counter() - t0
     byts = chain_step_cost(sysm, 8, 1, False)
+    cores = ocsr.num_threads()
+    # one step on one core: a one-product chain minus a chain with no product
+    ocsr.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        ocsr.chebyshev(Mt, Kc, 64, coef, k_stop=2)
+        t_set = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ocsr.chebyshev(Mt, Kc, 64, coef, k_stop=3)
+        one_core_ms = (time.perf_counter() - t0 - t_set) * 1e3
+    finally:
+        ocsr.set_num_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=round(byts * nprod / dt / 1e9, 3), unit="GB/s",
-                cores=ocsr.num_threads(), kind="oracle",
+                cores=cores, kind="oracle", cpu_model=model, nproc=os.cpu_count(),
+                one_core_ms_per_step=round(one_core_ms, 1),
+                one_core_value=round(byts / (one_core_ms / 1e3) / 1e9, 3),
                 sample=f"{nprod} Chebyshev steps (masked product + axpby + 1 float64 accumulator) "
                        f"of the oracle's scalar-CSR float64 chain on the same {sysm.n}-row H~ and "
                        f"kernel pattern; {dt:.1f} s; bytes per step counted as for the GPU "

@@ -44,6 +44,8 @@ def lib():
                                        ctypes.c_void_p, ctypes.c_int32]
         L.oracle_chebyshev.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -153,3 +155,7 @@ def chebyshev(Mt: Csr, K: Csr, n_pl: int, coefs: np.ndarray | None,
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))

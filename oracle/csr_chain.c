@@ -168,3 +168,13 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the parallel regions above (for timing on fewer cores). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
