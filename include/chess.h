@@ -162,13 +162,16 @@ typedef struct {
     double energy_wide;     /* adapt_kt: E' at kt_ratio times the returned kT */
     double kt_used;         /* kT of the returned K */
     int32_t kt_halvings;    /* adapt_kt: halvings of kT taken */
-    /* chess_fermi_operator: rough HOMO and LUMO in Ha from the same moments
+    /* chess_fermi_operator and, per system, chess_fermi_operator_batched:
+     * rough HOMO and LUMO in Ha from the same moments
      * (Sec. "Extraction of selected eigenvalues": the polynomials already
      * computed give such estimates almost for free).  With N_h = ceil(N_e)
      * states occupied, homo solves N(e) = N_h - 1/2 and lumo N(e) = N_h + 1/2
      * with the call's occupation function at the returned kT.  They are
      * accurate only for states isolated by several kT from their neighbours;
-     * NaN if N_h is 0 (homo) or n (lumo), and in the other entry points. */
+     * NaN if N_h is 0 (homo) or n (lumo), and in the other entry points.
+     * In a batch they come from the system's first attempt, or from the
+     * Gershgorin redo when its bounds were rejected. */
     double homo, lumo;
 } chess_info;
 

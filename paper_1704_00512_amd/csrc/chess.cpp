@@ -1428,6 +1428,23 @@ static double post_transform(chess_ctx *ctx, const Pattern *PK, const Frame &F, 
     return tr;
 }
 
+// HOMO / LUMO estimates from the moments of a density-kernel chain (Sec.
+// "Extraction of selected eigenvalues"): eigenvalue N solves N(e) = N - 1/2,
+// so with N_h = ceil(N_e) occupied states the HOMO solves N(e) = N_h - 1/2
+// and the LUMO N(e) = N_h + 1/2.  NaN past either end of the n states.
+static void homo_lumo(const hostmath::CountFunction &N, double n_e, double n_states, double lo,
+                      double hi, double kT, double *homo, double *lumo) {
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    const double nh = std::ceil(n_e - 1e-9);
+    const double tol = 1e-10 * std::max(1.0, n_e);
+    int it = 0;
+    *homo = *lumo = nan;
+    if (nh >= 1 && !hostmath::bisect_mu(N, nh - 0.5, tol, lo - 20 * kT, hi + 20 * kT, homo, &it))
+        *homo = nan;
+    if (nh + 1 <= n_states && !hostmath::bisect_mu(N, nh + 0.5, tol, lo - 20 * kT, hi + 20 * kT, lumo, &it))
+        *lumo = nan;
+}
+
 static void fill_info_defaults(chess_info *info) {
     if (!info) return;
     std::memset(info, 0, sizeof(*info));
@@ -1664,19 +1681,11 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         if (!br_given) br[0] = br[1] = nan;
     }
     }
-    // HOMO / LUMO estimates from the same moments (Sec. "Extraction of
-    // selected eigenvalues"): eigenvalue N solves N(e) = N - 1/2
     double homo = nan, lumo = nan;
     {
         hostmath::CountFunction Ng;
         Ng.init(mom, lo, hi, kT, o.smearing == CHESS_ERFC ? 0 : 1);
-        const double nh = std::ceil(n_e - 1e-9);
-        const double tol_g = 1e-10 * std::max(1.0, n_e);
-        int itg = 0;
-        if (nh >= 1 && !hostmath::bisect_mu(Ng, nh - 0.5, tol_g, lo - 20 * kT, hi + 20 * kT, &homo, &itg))
-            homo = nan;
-        if (nh + 1 <= (double)n && !hostmath::bisect_mu(Ng, nh + 0.5, tol_g, lo - 20 * kT, hi + 20 * kT, &lumo, &itg))
-            lumo = nan;
+        homo_lumo(Ng, n_e, (double)n, lo, hi, kT, &homo, &lumo);
     }
     const std::vector<double> c = hostmath::cheb_coeffs(occupation(o.smearing, mu, kT), lo, hi, n_pl);
     double ne_chain = 0.5 * c[0] * mom[0];
@@ -2153,6 +2162,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
     Ht.release();
     // per system: Eq. 6 and growth checks, mu from the moments, N at the trial mu
     std::vector<double> mu_star(nsys), ne_tr(3 * (size_t)nsys), pen(nsys);
+    std::vector<double> homo_s(nsys, nan), lumo_s(nsys, nan);
     std::vector<int> iters(nsys);
     std::vector<char> failed(nsys, 0);
     std::vector<int> failed_pos;
@@ -2183,6 +2193,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
             CHESS_THROW(CHESS_E_NOCONV, "system %d: N(mu) does not bracket %g electrons", idx[s], nes[s]);
         mu_star[s] = m;
         iters[s] = itn;
+        homo_lumo(N, nes[s], (double)PKs[s]->n(), lo[s], hi[s], kTs[s], &homo_s[s], &lumo_s[s]);
         for (int q = 0; q < 3; ++q) ne_tr[3 * (size_t)s + q] = N(mus[s][q]);
     }
     // K at the trial mu: K = P_K o (X P_K o (K' X)) over the batch, then per system
@@ -2238,6 +2249,8 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
             info->pred_lo = preds[s][0];
             info->pred_hi = preds[s][1];
             info->pred_mu = preds[s][2];
+            info->homo = homo_s[s];
+            info->lumo = lumo_s[s];
         }
     }
     HIPCHECK(hipStreamSynchronize(st));

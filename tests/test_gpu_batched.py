@@ -66,6 +66,9 @@ def test_batched_matches_oracle_per_system(gpu_ctx, precision, tol):
         _, oi = opl.fermi_operator(H, S, P, s.n_electrons, s.kT, s_bounds_=sb,
                                    n_pl_s=inf["n_pl_s"], h_bounds=hb, n_pl=inf["n_pl"])
         assert abs(inf["mu"] - oi["mu"]) < (1e-8 if precision == "f64" else 1e-5)
+        # HOMO / LUMO from the same moments
+        for k in ("homo", "lumo"):
+            assert abs(inf[k] - oi[k]) < (1e-8 if precision == "f64" else 1e-5), (s.n, k)
         assert r["ne_trial"][0] < r["ne_trial"][1] < r["ne_trial"][2]
 
 
