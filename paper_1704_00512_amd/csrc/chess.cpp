@@ -27,6 +27,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -654,6 +655,17 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
     return ctx->lplans.back().get();
 }
 
+// The product launchers keep, per kernel, a process-wide record of the
+// dynamic LDS limit they have raised (hipFuncSetAttribute); this lock keeps
+// that record consistent when contexts launch from several threads at once.
+static std::mutex g_launch_mu;
+
+static hipError_t launch_listed_locked(int dtype, int b, const ListedPlanDev &d, const ProductOperands &ops,
+                                       const Epilogue &ep, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    return launch_listed_product(dtype, b, d, ops, ep, st);
+}
+
 // C = P_C o (A Bt^T) with an epilogue.  A, Bt, C value arrays in dtype.
 static void product(chess_ctx *ctx, int dtype, const ProductPlan *plan, const void *a,
                     const void *bt, void *c, const Epilogue &ep) {
@@ -665,6 +677,7 @@ static void product(chess_ctx *ctx, int dtype, const ProductPlan *plan, const vo
     ops.bt_val = bt;
     ops.c_rp = plan->c->d_rp.as<int64_t>();
     ops.c_out = c;
+    std::lock_guard<std::mutex> lk(g_launch_mu);
     HIPCHECK(launch_masked_product(dtype, plan->a->b, plan->dev, ops, ep, ctx->stream));
 }
 
@@ -678,7 +691,7 @@ static void product_listed(chess_ctx *ctx, int dtype, const ListedPlan *plan, co
     ops.bt_val = bt;
     ops.c_rp = plan->c->d_rp.as<int64_t>();
     ops.c_out = c;
-    HIPCHECK(launch_listed_product(dtype, plan->a->b, plan->dev, ops, ep, ctx->stream));
+    HIPCHECK(launch_listed_locked(dtype, plan->a->b, plan->dev, ops, ep, ctx->stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -866,9 +879,9 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
         ListedPlanDev d = lp->dev;
         d.variant = v;
         if (!listed_product_variant_ok(dtype, b, d, v) || listed_product_lds_bytes(dtype, b, d) > 160 * 1024) continue;
-        HIPCHECK(launch_listed_product(dtype, b, d, ops, ep, st));
+        HIPCHECK(launch_listed_locked(dtype, b, d, ops, ep, st));
         tm.start();
-        for (int r = 0; r < 3; ++r) HIPCHECK(launch_listed_product(dtype, b, d, ops, ep, st));
+        for (int r = 0; r < 3; ++r) HIPCHECK(launch_listed_locked(dtype, b, d, ops, ep, st));
         const double ms = tm.stop();
         if (v == 0 || ms < best) {
             best = ms;
