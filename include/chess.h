@@ -31,7 +31,8 @@
  * Work is ordered on the context's stream.  Every entry point returns after
  * the stream has drained (results that reach the host, such as mu or
  * eigenvalues, need that anyway), so outputs are ready on return.  A context
- * must not be used by two threads at once.
+ * must not be used by two threads at once; different contexts (on one device
+ * or several) may be used from different threads at the same time.
  *
  * Errors: every call returns CHESS_OK (0) or a negative CHESS_E_* code; then
  * chess_last_error() describes it and the outputs are undefined.
