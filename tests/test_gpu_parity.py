@@ -237,6 +237,47 @@ def test_fermi_operator_dense_matches_diagonalisation(gpu_ctx):
     assert abs(info["tr_ks"] - s.n_electrons) < 1e-9
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_fermi_dirac_fixed_parameters(gpu_ctx, precision, tol):
+    # Eq. 9 occupation (smearing = Fermi-Dirac) against the oracle's
+    s = system(*SYS4, kT=0.02)
+    K, info = chess_fermi_operator(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h),
+                                   gpat(s.pat_k), s.n_electrons, s.kT, precision=precision,
+                                   smearing="fermi_dirac", mu=-0.95, **FIX)
+    Ko, oinfo = oracle_fermi(s, smearing="fd", s_bounds_=FIX["s_bounds"], n_pl_s=FIX["n_pl_s"],
+                             h_bounds=FIX["bounds"], n_pl=FIX["n_pl"], mu=-0.95)
+    assert np.max(np.abs(K.cpu().numpy() - Ko)) < tol
+    assert abs(info["tr_ks"] - oinfo["trKS"]) < tol * s.n
+
+
+def test_fermi_dirac_mu_search(gpu_ctx):
+    s = system(*SYS4, kT=0.02)
+    K, info = chess_fermi_operator(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h),
+                                   gpat(s.pat_k), s.n_electrons, s.kT, precision="f64",
+                                   smearing="fermi_dirac", tol_ne=1e-11, **FIX)
+    Ko, oinfo = oracle_fermi(s, smearing="fd", s_bounds_=FIX["s_bounds"], n_pl_s=FIX["n_pl_s"],
+                             h_bounds=FIX["bounds"], n_pl=FIX["n_pl"], tol_ne=1e-11)
+    assert abs(info["mu"] - oinfo["mu"]) < 1e-9
+    assert np.max(np.abs(K.cpu().numpy() - Ko)) < 1e-8
+    assert abs(info["homo"] - oinfo["homo"]) < 1e-8 and abs(info["lumo"] - oinfo["lumo"]) < 1e-8
+
+
+def test_fermi_dirac_dense_matches_diagonalisation(gpu_ctx):
+    # no truncation on dense patterns: the exact Fermi-Dirac density kernel up
+    # to the polynomial error, with mu from the library's own search
+    s = system(64, 4, 10.0, 14.0, 0, kT=0.03)
+    Hd, Sd = g.to_dense(s.pat_h, s.H), g.to_dense(s.pat_h, s.S)
+    Kd, mu, ev = odense.density_kernel(Hd, Sd, s.n_electrons, s.kT, smearing="fd")
+    K, info = chess_fermi_operator(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h),
+                                   gpat(s.pat_k), s.n_electrons, s.kT, precision="f64",
+                                   smearing="fermi_dirac", s_bounds=(0.299, 2.001),
+                                   bounds=(ev[0] - 1e-3, ev[-1] + 1e-3), tol_fit=1e-13,
+                                   tol_fit_s=1e-13, tol_ne=1e-12)
+    assert abs(info["mu"] - mu) < 1e-10
+    assert np.max(np.abs(K.cpu().numpy() - g.from_dense(s.pat_k, Kd))) < TOL64
+    assert abs(info["tr_ks"] - s.n_electrons) < 1e-9
+
+
 @pytest.mark.parametrize("a", [-1.0, -0.5, 0.5])
 def test_matrix_power_parity(gpu_ctx, a):
     s = system(*SYS4)
