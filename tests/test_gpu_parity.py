@@ -9,6 +9,7 @@ import math
 
 import numpy as np
 import pytest
+import scipy.linalg
 import torch
 
 from oracle import csr as ocsr
@@ -279,12 +280,16 @@ def test_fermi_dirac_dense_matches_diagonalisation(gpu_ctx):
 
 
 @pytest.mark.parametrize("a", [-1.0, -0.5, 0.5])
-def test_matrix_power_parity(gpu_ctx, a):
-    s = system(*SYS4)
+@pytest.mark.parametrize("spec", [SYS4, SYS9])
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_matrix_power_parity(gpu_ctx, a, spec, precision, tol):
+    # S is scaled to the spectrum [0.3, 2.0] by the generator
+    s = system(*spec)
     R, info = chess_matrix_power(gpu_ctx, dt(s.S), gpat(s.pat_h), a, gpat(s.pat_k),
-                                 precision="f64", s_bounds=(0.25, 2.05), n_pl=48)
+                                 precision=precision, s_bounds=(0.25, 2.05), n_pl_s=48)
+    assert info["n_pl_s"] == 48
     Ro, _ = opl.matrix_power(bm(s.pat_h, s.S), a, bm(s.pat_k), bounds=(0.25, 2.05), n_pl=48)
-    assert np.max(np.abs(R.cpu().numpy() - Ro)) < TOL64
+    assert np.max(np.abs(R.cpu().numpy() - Ro)) < tol
 
 
 def test_matrix_power_estimated_bounds(gpu_ctx):
@@ -307,6 +312,23 @@ def test_eigs_in_interval_parity(gpu_ctx):
                                       hi, gpat(s.pat_k), precision="f64", eig_width=width,
                                       n_pl=n_pl, s_bounds=(0.25, 2.05), n_pl_s=40,
                                       bounds=(-1.9, 0.1))
+    ref, _ = opl.eigs_in_interval(bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k), lo, hi,
+                                  width=width, s_bounds_=(0.25, 2.05), n_pl_s=40,
+                                  h_bounds=(-1.9, 0.1), n_pl=n_pl)
+    assert ev.shape == ref.shape and ev.shape[0] > 5
+    assert np.max(np.abs(ev - ref)) < 1e-8
+
+
+def test_eigs_in_interval_parity_b9(gpu_ctx):
+    # 9 x 9 blocks: H' of this system lies in [-1.70, -0.30]; a fixed degree
+    # and an interval of about ten eigenvalues keep the oracle's bisections short
+    s = system(*SYS9)
+    lo, hi, width, n_pl = -0.95, -0.93, 3e-3, 1200
+    ev, info = chess_eigs_in_interval(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h), lo,
+                                      hi, gpat(s.pat_k), precision="f64", eig_width=width,
+                                      n_pl=n_pl, s_bounds=(0.25, 2.05), n_pl_s=40,
+                                      bounds=(-1.9, 0.1))
+    print(f"[gpu-parity] b9 eigenvalues: {ev.shape[0]} from the library", flush=True)
     ref, _ = opl.eigs_in_interval(bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k), lo, hi,
                                   width=width, s_bounds_=(0.25, 2.05), n_pl_s=40,
                                   h_bounds=(-1.9, 0.1), n_pl=n_pl)
