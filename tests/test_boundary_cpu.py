@@ -104,3 +104,70 @@ def test_pattern_index_types_are_checked_before_the_call():
         BlockPattern(b=4, nb=2, row_ptr=rp, col_idx=ci).c()
     with pytest.raises(ValueError, match="CUDA"):
         BlockPattern(b=4, nb=2, row_ptr=rp.long(), col_idx=ci).c()
+
+
+C_SSF_CALLER = r'''
+#include <stdio.h>
+#include "chess.h"
+/* a 4 x 4 matrix in b = 2 blocks; the third segment runs from row 3 into row 4 */
+static const int64_t KEYG[4][4] = {{1, 2, 1, 1}, {1, 3, 2, 2}, {2, 2, 3, 4}, {3, 4, 4, 4}};
+static const double VAL[12] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12};
+int main(void) {
+  int64_t nnzb = -1, rp[3], nseg = 0, nv = 0, kg[16][4], kv[16];
+  int32_t ci[4];
+  double vb[16], v2[64];
+  int rc = chess_ssf_to_bcsr(2, 4, 4, &KEYG[0][0], NULL, VAL, 12, NULL, NULL, NULL, 0, &nnzb);
+  rc |= chess_ssf_to_bcsr(2, 4, 4, &KEYG[0][0], NULL, VAL, 12, rp, ci, vb, 4, &nnzb);
+  printf("%d %lld\n", rc, (long long)nnzb);
+  for (int i = 0; i < 3; ++i) printf("%lld ", (long long)rp[i]);
+  printf("\n");
+  for (int i = 0; i < nnzb; ++i) printf("%d ", ci[i]);
+  printf("\n");
+  for (int i = 0; i < nnzb * 4; ++i) printf("%.17g ", vb[i]);
+  printf("\n");
+  rc = chess_bcsr_to_ssf(2, 2, rp, ci, vb, NULL, NULL, NULL, 0, &nseg, &nv);
+  rc |= chess_bcsr_to_ssf(2, 2, rp, ci, vb, &kg[0][0], kv, v2, 16, &nseg, &nv);
+  printf("%d %lld %lld\n", rc, (long long)nseg, (long long)nv);
+  for (int s = 0; s < nseg; ++s)
+    printf("%lld %lld %lld %lld %lld ", (long long)kg[s][0], (long long)kg[s][1],
+           (long long)kg[s][2], (long long)kg[s][3], (long long)kv[s]);
+  printf("\n");
+  for (int i = 0; i < nv; ++i) printf("%.17g ", v2[i]);
+  printf("\n");
+  return 0;
+}
+'''
+
+
+def test_c_program_calls_the_ssf_conversions(lib):
+    # a plain C caller linked against libchess.so (host code only, no GPU),
+    # checked against the oracle's conversions through dense matrices
+    import tempfile
+
+    import numpy as np
+
+    from oracle import ssf as ossf
+    from paper_1704_00512_amd import _lib
+    pkg = os.path.dirname(_lib.LIB_PATH)
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "c.c"), os.path.join(d, "c")
+        open(src, "w").write(C_SSF_CALLER)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-L", pkg, "-lchess",
+                        f"-Wl,-rpath,{pkg}", "-Wl,-rpath-link,/opt/rocm/lib", "-o", exe],
+                       check=True)
+        lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.splitlines()
+    rc, nnzb = map(int, lines[0].split())
+    assert rc == 0 and nnzb == 4
+    keyg = np.array([[1, 2, 1, 1], [1, 3, 2, 2], [2, 2, 3, 4], [3, 4, 4, 4]])
+    D, M = ossf.ssf_to_dense(4, keyg, None, np.arange(1.0, 13.0))
+    rp, ci, vb = ossf.dense_to_bcsr(D, M, 2)
+    assert [int(x) for x in lines[1].split()] == list(rp)
+    assert [int(x) for x in lines[2].split()] == list(ci)
+    assert np.array_equal(np.array(lines[3].split(), dtype=float), vb.ravel())
+    rc, nseg, nv = map(int, lines[4].split())
+    D2, M2 = ossf.bcsr_to_dense(2, 2, rp, ci, vb)
+    kg2, kv2, v2 = ossf.dense_to_ssf(D2, M2)
+    assert rc == 0 and nseg == len(kg2) and nv == len(v2)
+    segs = np.array(lines[5].split(), dtype=np.int64).reshape(-1, 5)
+    assert np.array_equal(segs[:, :4], np.asarray(kg2)) and np.array_equal(segs[:, 4], kv2)
+    assert np.array_equal(np.array(lines[6].split(), dtype=float), v2)
