@@ -294,6 +294,26 @@ int chess_mlp_adam(chess_ctx *ctx, float *params, const float *grad, float *m, f
 int chess_model_load(chess_ctx *ctx, const float *blob, int64_t n);
 int chess_model_save(const chess_ctx *ctx, float *blob, int64_t n);
 
+/*
+ * Degree rule of Eq. 7 (Sec. "Determination of the eigenvalue bounds and
+ * polynomial degree"), host only, no context, no device work: the smallest
+ * n_pl, a multiple of 8 up to 20000, whose Eq. 5 interpolant p of f on
+ * [lo, hi] has max |p - f| < tol_fit over max(8192, 8 n_pl) Chebyshev-Lobatto
+ * points of [lo, hi].  The entry points above use this rule wherever n_pl or
+ * n_pl_s is not given.
+ *   fn     : CHESS_FN_ERFC or CHESS_FN_FERMI_DIRAC: the occupation (Eq. 11 or
+ *            Eq. 9) of width kT = param centred at mu = (lo + hi)/2, where the
+ *            Chebyshev nodes are sparsest (the degree used for any mu);
+ *            CHESS_FN_POWER: x^param (Sec. "Matrix powers"), lo > 0 needed
+ *            unless param is a non-negative integer
+ *   n_pl_out : host, receives the degree
+ * Returns CHESS_E_ARG for an unknown fn, hi <= lo, tol_fit <= 0, param <= 0
+ * for an occupation, lo <= 0 for a non-integer power, or a null n_pl_out;
+ * CHESS_E_NOCONV when 20000 terms do not reach tol_fit.
+ */
+enum { CHESS_FN_ERFC = 0, CHESS_FN_FERMI_DIRAC = 1, CHESS_FN_POWER = 2 };
+int chess_degree(int32_t fn, double param, double lo, double hi, double tol_fit, int32_t *n_pl_out);
+
 /* Fills *opts with the defaults listed above. */
 void chess_default_opts(chess_opts *opts);
 

@@ -26,8 +26,17 @@ Readings of points the paper leaves open (each is listed in the design notes):
   R5  erfc occupation f = 1/2 erfc((e - mu)/kT), i.e. beta = 1/kT; Fermi-Dirac
       f = 1/(1 + exp((e - mu)/kT));
   R6  occupations in [0, 1], no spin factor;
-  R8  Eq. 7's threshold is called tol_fit; the max is taken on 8192
-      Chebyshev-Lobatto points of [lo, hi]; m runs over 8, 16, 24, ...
+  R7  Eq. 6 is evaluated in the scaled variable with the bounds at -1 and 1
+      and alpha = -200, so an eigenvalue at a bound contributes 1; the check
+      fails when some |Tr T_k| exceeds 1.01 n (growth test; the side then
+      comes from the moments' sign pattern), else when |Tr W^p| > 0.5 (only
+      when the n-term fit of f^p is good: n times its error, judged on
+      min(n, 1024) terms, below 0.1; the sign picks the side); the failing
+      side moves out by 10 % of the width;
+  R8  Eq. 7's threshold is called tol_fit; the max is taken on
+      max(8192, 8 m) Chebyshev-Lobatto points of [lo, hi], a grid that
+      grows with m so that the error curve of p_m (about m oscillations) is
+      sampled 8 times per oscillation; m runs over 8, 16, 24, ...
   R10 mu by bisection on [lo, hi];
   R12 eigenvalue indices N with N(lo) < N - 1/2 < N(hi), ascending.
 """
@@ -116,22 +125,126 @@ def lobatto_grid(lo: float, hi: float, npts: int = 8192) -> np.ndarray:
     return np.cos(math.pi * np.arange(npts) / (npts - 1)) / sigma + tau
 
 
-def fit_error(f, lo: float, hi: float, m: int, npts: int = 8192) -> float:
-    sigma, tau = scale_shift(lo, hi)
+def fit_points(m: int) -> int:
+    """Reading R8: number of Lobatto points on which Eq. 7's max is taken."""
+    return max(8192, 8 * m)
+
+
+def cheb_eval_lobatto(c: np.ndarray, npts: int) -> np.ndarray:
+    """Eq. 1 for scalars at the Lobatto points x_i = cos(pi i/(npts-1)):
+    c_0/2 + sum_j c_j cos(pi i j/(npts-1)), which is a DCT-I (library
+    routine) of (c_0/2, c_1/2, ..., c_{m-1}/2, 0, ..., 0)."""
+    import scipy.fft
+    assert npts - 1 >= c.shape[0]
+    a = np.zeros(npts)
+    a[:c.shape[0]] = 0.5 * c
+    a[0] = 0.5 * c[0]
+    # scipy's DCT-I: y_i = a_0 + (-1)^i a_{N-1} + 2 sum_{j=1}^{N-2} a_j cos(pi i j/(N-1))
+    return scipy.fft.dct(a, type=1)
+
+
+def fit_error(f, lo: float, hi: float, m: int, npts: int | None = None) -> float:
+    """Eq. 7's max |p_m - f| over the Lobatto grid of reading R8 (npts points,
+    default fit_points(m)); p_m is the Eq. 5 interpolant with m terms."""
+    npts = fit_points(m) if npts is None else npts
     x = lobatto_grid(lo, hi, npts)
     c = cheb_coeffs(f, lo, hi, m)
-    return float(np.max(np.abs(cheb_eval(c, sigma * (x - tau)) - f(x))))
+    if npts - 1 >= m:
+        p = cheb_eval_lobatto(c, npts)
+    else:  # a grid coarser than the expansion (only to show what it misses)
+        sigma, tau = scale_shift(lo, hi)
+        p = cheb_eval(c, sigma * (x - tau))
+    return float(np.max(np.abs(p - f(x))))
 
 
 def degree(f, lo: float, hi: float, tol_fit: float, step: int = 8,
-           m_max: int = 4000, npts: int = 8192) -> int:
-    """Eq. 7: the smallest m (m = step, 2 step, ...) with max|p_m - f| < tol_fit."""
-    m = step
+           m_max: int = 4000, npts: int | None = None, m_start: int | None = None) -> int:
+    """Eq. 7: the smallest m (m = step, 2 step, ...) with max|p_m - f| < tol_fit.
+
+    m_start (a multiple of step) starts the scan later; it is only for
+    callers that already know every smaller m fails."""
+    m = step if m_start is None else m_start
     while m <= m_max:
         if fit_error(f, lo, hi, m, npts) < tol_fit:
             return m
         m += step
     raise ValueError("no degree up to m_max meets tol_fit")
+
+
+# ----------------------------------------------------------------------------
+# Eq. 6: the check of the spectral bounds (reading R7)
+# ----------------------------------------------------------------------------
+
+PENALTY_ALPHA = -200.0
+
+
+def penalty_trace(t: np.ndarray, alpha: float = PENALTY_ALPHA) -> float:
+    """Tr W^p of Eq. 6 from the moments t_k = Tr T_k(M~) of the scaled matrix:
+    W^p = c_0/2 I + sum_j c_j T_j(M~) with c the Eq. 5 coefficients of
+    f^p(x) = exp(alpha (x + 1)) - exp(-alpha (x - 1)) on [-1, 1], as many as
+    there are moments."""
+    t = np.asarray(t, dtype=np.float64)
+    c = cheb_coeffs(penalty_fn(alpha, -1.0, 1.0), -1.0, 1.0, t.shape[0])
+    return trace_from_moments(c, t)
+
+
+def penalty_valid(n_terms: int, n_rows: int, alpha: float = PENALTY_ALPHA) -> bool:
+    """Reading R7: Eq. 6 is trusted only when n_rows times the fit error of
+    f^p (with min(n_terms, 1024) terms) is below 0.1."""
+    m = min(n_terms, 1024)
+    return fit_error(penalty_fn(alpha, -1.0, 1.0), -1.0, 1.0, m) * n_rows < 0.1
+
+
+def growth_ok(t: np.ndarray, n_rows: int) -> bool:
+    """|T_k(x)| <= 1 on [-1, 1], so |Tr T_k| <= n whenever every eigenvalue of
+    M~ is inside the bounds; reading R7 allows 1 %."""
+    t = np.asarray(t, dtype=np.float64)
+    return bool(np.all(np.isfinite(t)) and np.all(np.abs(t) <= 1.01 * n_rows))
+
+
+def moment_side(t: np.ndarray) -> str:
+    """Side of an eigenvalue far outside the bounds, from the moments alone:
+    for x < -1, T_k(x) = (-1)^k cosh(k arccosh|x|) alternates in sign, for
+    x > 1 it keeps one sign, and it grows fastest at the largest k.  Over the
+    last 16 moments, 'lo' when the alternating sum is the larger one."""
+    t = np.asarray(t, dtype=np.float64)
+    k = np.arange(max(0, t.shape[0] - 16), t.shape[0])
+    tt = np.nan_to_num(t[k], nan=0.0, posinf=1e300, neginf=-1e300)
+    alt = abs(float(np.sum(np.where(k % 2 == 0, tt, -tt))))
+    same = abs(float(np.sum(tt)))
+    return "lo" if alt > same else "hi"
+
+
+def bounds_check(t: np.ndarray, n_rows: int) -> dict:
+    """Eq. 6 and the growth test on the moments of one chain (reading R7).
+
+    The growth test comes first: an eigenvalue clearly outside the bounds
+    makes some |Tr T_k| exceed 1.01 n, and then the rounding noise of the
+    penalty coefficients times that growth decides the penalty's value, so
+    the side comes from the moments' sign pattern (moment_side).  With the
+    growth test passed, Eq. 6 (when its fit is valid) catches eigenvalues at
+    or just beyond a bound and its sign picks the side: positive for the
+    lower bound, negative for the upper one.
+
+    Returns ok, the penalty (NaN when not evaluated) and, when not ok, the
+    side to move: 'lo' or 'hi'."""
+    if not growth_ok(t, n_rows):
+        return dict(ok=False, penalty=math.nan, valid=False, side=moment_side(t))
+    valid = penalty_valid(len(t), n_rows)
+    pen = penalty_trace(t) if valid else math.nan
+    ok = not (valid and abs(pen) > 0.5)
+    side = None if ok else ("lo" if pen > 0 else "hi")
+    return dict(ok=ok, penalty=pen, valid=valid, side=side)
+
+
+def widen(lo: float, hi: float, side: str) -> tuple[float, float]:
+    """Reading R7: move the failing side out by 10 % of the width."""
+    w = hi - lo
+    if side in ("lo", "both"):
+        lo -= 0.1 * w
+    if side in ("hi", "both"):
+        hi += 0.1 * w
+    return lo, hi
 
 
 # ----------------------------------------------------------------------------

@@ -93,25 +93,63 @@ def s_bounds(S: Csr, lanczos_k: int = 60, margin: float = 1e-3) -> tuple[float, 
     return lo, ghi
 
 
+def widen_power(lo: float, hi: float) -> tuple[float, float]:
+    """Reading R7 for matrix powers (growth test only): both sides move out by
+    10 % of the width, the lower bound at most halved so that it stays
+    positive for non-integer or negative exponents."""
+    w = hi - lo
+    return max(lo - 0.1 * w, 0.5 * lo), hi + 0.1 * w
+
+
 def matrix_power(S: BlockMat, a: float, pattern: BlockMat, bounds=None, n_pl=None,
-                 tol_fit: float = 1e-12, extra_powers=()):
+                 tol_fit: float = 1e-12, extra_powers=(), max_reexpand: int = 3):
     """Sec. "Matrix powers": S^a on `pattern` by the chain with f = x^a.
     Returns (values [nnzb, b, b], info) (and extra powers from the same chain
-    when `extra_powers` is given: a dict a' -> values)."""
+    when `extra_powers` is given: a dict a' -> values).
+
+    Sec. "Determination of the eigenvalue bounds and polynomial degree": a
+    chain whose moments fail the growth test (an eigenvalue outside the
+    bounds) is redone with widened bounds (widen_power), at most
+    max_reexpand times; info['reexpansions'] counts them."""
     Sc = S.csr()
     K = pattern.pattern_csr()
     lo, hi = bounds if bounds is not None else s_bounds(Sc)
     powers = (a,) + tuple(extra_powers)
-    if n_pl is None:
-        n_pl = max(cb.degree(cb.power_fn(p), lo, hi, tol_fit) for p in powers)
-    coefs = np.stack([cb.cheb_coeffs(cb.power_fn(p), lo, hi, n_pl) for p in powers])
-    acc, mom = chebyshev(scaled(Sc, lo, hi), K, n_pl, coefs)
+    n_given = n_pl
+    reexp = 0
+    while True:
+        if n_given is None:
+            n_pl = max(cb.degree(cb.power_fn(p), lo, hi, tol_fit) for p in powers)
+        coefs = np.stack([cb.cheb_coeffs(cb.power_fn(p), lo, hi, n_pl) for p in powers])
+        acc, mom = chebyshev(scaled(Sc, lo, hi), K, n_pl, coefs)
+        if cb.growth_ok(mom, K.n):
+            break
+        if reexp >= max_reexpand:
+            raise ValueError(f"bounds [{lo}, {hi}] still fail the growth test")
+        lo, hi = widen_power(lo, hi)
+        reexp += 1
     # left-multiplication chain -> values are those of p(S~) directly
     outs = [pattern.to_block(acc[q]) for q in range(len(powers))]
-    info = dict(lo=lo, hi=hi, n_pl=n_pl, moments=mom)
+    info = dict(lo=lo, hi=hi, n_pl=n_pl, moments=mom, reexpansions=reexp)
     if extra_powers:
         return outs[0], info, {p: o for p, o in zip(extra_powers, outs[1:])}
     return outs[0], info
+
+
+def frame_products(H: Csr, X: Csr, K: Csr) -> Csr:
+    """Step 3: H' = P_H o (X P_K o (H X)) (reading R4: the inner product on
+    the kernel pattern, the outer one on the pattern of H), symmetrised."""
+    Z = K.with_values(masked_spgemm(H, X, K))           # P_K o (H X)
+    Hp = H.with_values(masked_spgemm(X, Z, H))          # P_H o (X Z)
+    return symmetrised(Hp)
+
+
+def post_transform(Kp: Csr, X: Csr, K: Csr) -> Csr:
+    """Step 9: K = P_K o (X P_K o (K' X)), both products on the kernel
+    pattern (the post-processing S^-1/2 p S^-1/2 of Sec. "Fermi Operator
+    Expansion")."""
+    W = K.with_values(masked_spgemm(Kp, X, K))          # P_K o (K' X)
+    return K.with_values(masked_spgemm(X, W, K))         # P_K o (X W)
 
 
 def orthogonal_frame(H: BlockMat, S: BlockMat, pattern: BlockMat, s_bnds=None, n_pl_s=None,
@@ -120,18 +158,15 @@ def orthogonal_frame(H: BlockMat, S: BlockMat, pattern: BlockMat, s_bnds=None, n
     Xv, sinfo = matrix_power(S, -0.5, pattern, bounds=s_bnds, n_pl=n_pl_s, tol_fit=tol_fit_s)
     K = pattern.pattern_csr()
     X = K.with_values(block_values_to_csr(pattern.nb, pattern.b, pattern.row_ptr, Xv))
-    Hc = H.csr()
-    Z = K.with_values(masked_spgemm(Hc, X, K))          # P_K o (H X)
-    Hp = Hc.with_values(masked_spgemm(X, Z, Hc))        # P_H o (X Z)
-    Hp = symmetrised(Hp)
-    return X, Hp, sinfo
+    return X, frame_products(H.csr(), X, K), sinfo
 
 
 def fermi_operator(H: BlockMat, S: BlockMat, pattern: BlockMat, n_e: float, kT: float,
                    smearing: str = "erfc", s_bounds_=None, n_pl_s=None, h_bounds=None,
                    n_pl=None, mu=None, tol_fit: float = 1e-12, tol_fit_s: float = 1e-12,
                    tol_ne: float | None = None, adapt_kt: bool = False, kt_ratio: float = 1.25,
-                   tol_energy: float | None = None, max_kt_halvings: int = 4):
+                   tol_energy: float | None = None, max_kt_halvings: int = 4,
+                   max_reexpand: int = 3):
     """Steps 1-9.  Returns (K values [nnzb_K, b, b], info dict).
 
     adapt_kt: the width check of Sec. "Fermi Operator Expansion": after mu is
@@ -139,7 +174,12 @@ def fermi_operator(H: BlockMat, S: BlockMat, pattern: BlockMat, n_e: float, kT: 
     for the same N) gives E'; if |E - E'| > tol_energy the width is halved and
     the expansion redone (a new degree unless n_pl is given), at most
     max_kt_halvings times.  E and E' come from the moments of the same chain
-    (energy_from_moments), which runs one term longer for that."""
+    (energy_from_moments), which runs one term longer for that.
+
+    The bounds of H' (given or Gershgorin) are checked by Eq. 6 and the
+    growth test on the moments of each chain (reading R7); a failure moves
+    the failing side out by 10 % of the width and redoes the expansion, at
+    most max_reexpand times (info['reexpansions'], info['penalty'])."""
     X, Hp, sinfo = orthogonal_frame(H, S, pattern, s_bounds_, n_pl_s, tol_fit_s)
     K = pattern.pattern_csr()
     lo, hi = h_bounds if h_bounds is not None else cb.gershgorin(Hp.to_scipy())
@@ -151,9 +191,24 @@ def fermi_operator(H: BlockMat, S: BlockMat, pattern: BlockMat, n_e: float, kT: 
     n_pl_given = n_pl
     halvings = 0
     energy = energy_wide = float("nan")
+    reexp = 0
+    penalty = float("nan")
     while True:
-        n_pl = n_pl_given if n_pl_given is not None else cb.degree(lambda e: occ(e, tau, kT), lo, hi, tol_fit)
-        _, mom_e = chebyshev(Ht, K, n_pl + 1 if adapt_kt else n_pl, None)
+        # step 5-6, checked by Eq. 6 and the growth test (reading R7): the
+        # failing side moves out and the expansion is redone
+        while True:
+            sigma, tau = cb.scale_shift(lo, hi)
+            Ht = scaled(Hp, lo, hi)
+            n_pl = n_pl_given if n_pl_given is not None else cb.degree(lambda e: occ(e, tau, kT), lo, hi, tol_fit)
+            _, mom_e = chebyshev(Ht, K, n_pl + 1 if adapt_kt else n_pl, None)
+            chk = cb.bounds_check(mom_e, K.n)
+            penalty = chk["penalty"]
+            if chk["ok"]:
+                break
+            if reexp >= max_reexpand:
+                raise ValueError(f"bounds [{lo}, {hi}] still fail after {reexp} widenings")
+            lo, hi = cb.widen(lo, hi, chk["side"])
+            reexp += 1
         mom = mom_e[:n_pl]
         it = 0
         mu_k = mu
@@ -175,16 +230,15 @@ def fermi_operator(H: BlockMat, S: BlockMat, pattern: BlockMat, n_e: float, kT: 
     homo, lumo = cb.homo_lumo_from_moments(mom, lo, hi, kT, n_e, smearing)
     c = cb.cheb_coeffs(lambda e: occ(e, mu, kT), lo, hi, n_pl)
     acc, _ = chebyshev(Ht, K, n_pl, c[None, :])
-    Kp = K.with_values(acc[0])
-    W = K.with_values(masked_spgemm(Kp, X, K))          # P_K o (K' X)
-    Kv = masked_spgemm(X, W, K)                          # P_K o (X W)
-    Kfin = K.with_values(Kv)
+    Kfin = post_transform(K.with_values(acc[0]), X, K)
+    Kv = Kfin.v
     Sc = S.csr()
     trKS = float(Kfin.to_scipy().multiply(Sc.to_scipy()).sum())
     info = dict(mu=mu, lo=lo, hi=hi, n_pl=n_pl, n_pl_s=sinfo["n_pl"], s_lo=sinfo["lo"],
                 s_hi=sinfo["hi"], moments=mom, bisect_iters=it, trKS=trKS,
                 ne_chain=cb.trace_from_moments(c, mom), energy=energy,
-                energy_wide=energy_wide, kT=kT, kt_halvings=halvings, homo=homo, lumo=lumo)
+                energy_wide=energy_wide, kT=kT, kt_halvings=halvings, homo=homo, lumo=lumo,
+                reexpansions=reexp, penalty=penalty)
     return pattern.to_block(Kv), info
 
 

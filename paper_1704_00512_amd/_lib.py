@@ -16,6 +16,7 @@ CHESS_OK = 0
 CHESS_F64, CHESS_F32 = 0, 1
 CHESS_ERFC, CHESS_FERMI_DIRAC = 0, 1
 CHESS_BOUNDS_GERSHGORIN, CHESS_BOUNDS_LANCZOS = 0, 1
+CHESS_FN_ERFC, CHESS_FN_FERMI_DIRAC, CHESS_FN_POWER = 0, 1, 2
 
 ERRORS = {
     -1: "CHESS_E_ARG", -2: "CHESS_E_PATTERN", -3: "CHESS_E_NOT_SPD", -4: "CHESS_E_BOUNDS",
@@ -86,7 +87,7 @@ EXPORTS = ["chess_default_opts", "chess_create", "chess_destroy", "chess_last_er
            "chess_chebyshev", "chess_masked_product", "chess_set_progress",
            "chess_features", "chess_mlp_forward", "chess_mlp_grad", "chess_mlp_adam",
            "chess_model_load", "chess_model_save", "chess_fermi_operator_batched",
-           "chess_ssf_to_bcsr", "chess_bcsr_to_ssf"]
+           "chess_ssf_to_bcsr", "chess_bcsr_to_ssf", "chess_degree"]
 
 N_FEATURES, MLP_HIDDEN, MLP_OUT = 64, 128, 3
 MLP_PARAMS = MLP_HIDDEN * N_FEATURES + MLP_HIDDEN + MLP_OUT * MLP_HIDDEN + MLP_OUT
@@ -146,6 +147,8 @@ def load():
     i64, i32 = ctypes.c_int64, ctypes.c_int32
     L.chess_ssf_to_bcsr.argtypes = [i32, i64, i64, vp, vp, vp, i64, vp, vp, vp, i64, P(i64)]
     L.chess_bcsr_to_ssf.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i64, P(i64), P(i64)]
+    L.chess_degree.argtypes = [i32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, P(i32)]
     for name in EXPORTS:
         if name not in ("chess_default_opts", "chess_last_error"):
             getattr(L, name).restype = ctypes.c_int

@@ -403,3 +403,20 @@ def chess_bcsr_to_ssf(b: int, row_ptr, col_idx, val):
     if rc != 0:
         raise ChessError(rc, "chess_bcsr_to_ssf failed")
     return kg[:nseg.value], kv[:nseg.value], v[:nval.value]
+
+
+_FN = {"erfc": _lib.CHESS_FN_ERFC, "fermi_dirac": _lib.CHESS_FN_FERMI_DIRAC,
+       "power": _lib.CHESS_FN_POWER}
+
+
+def chess_degree(fn: str, param: float, lo: float, hi: float, tol_fit: float) -> int:
+    """Eq. 7's degree for an occupation of width param (fn "erfc" or
+    "fermi_dirac", centred on [lo, hi]) or for x^param (fn "power"); host
+    only.  Raises ChessError with the library's code."""
+    L = _lib.load()
+    out = ctypes.c_int32(0)
+    rc = L.chess_degree(_FN[fn], float(param), float(lo), float(hi), float(tol_fit),
+                        ctypes.byref(out))
+    if rc != 0:
+        raise ChessError(rc, "chess_degree")
+    return int(out.value)

@@ -1196,7 +1196,7 @@ static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *
         if (n_pl <= 0) {
             n_pl = 1;
             for (double a : powers) {
-                const int m = hostmath::degree([a](double x) { return std::pow(x, a); }, r.lo, r.hi, tol, 8, 20000, 2048);
+                const int m = hostmath::degree([a](double x) { return std::pow(x, a); }, r.lo, r.hi, tol, 8, 20000);
                 if (m < 0) CHESS_THROW(CHESS_E_NOCONV, "no degree up to 20000 reaches tol_fit %g for x^%g", tol, a);
                 n_pl = std::max(n_pl, m);
             }
@@ -1578,7 +1578,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         hostmath::scale_shift(lo, hi, &sigma, &tau);
         n_pl = o.n_pl;
         if (n_pl <= 0) {
-            n_pl = hostmath::degree(occupation(o.smearing, tau, kT), lo, hi, o.tol_fit, 8, 20000, 2048);
+            n_pl = hostmath::degree(occupation(o.smearing, tau, kT), lo, hi, o.tol_fit, 8, 20000);
             if (n_pl < 0) CHESS_THROW(CHESS_E_NOCONV, "no degree up to 20000 reaches tol_fit %g", o.tol_fit);
         }
         HIPCHECK(launch_scale_shift(b, PH->nnzb, PH->d_brow.as<int32_t>(), PH->d_ci.as<int32_t>(), F.Hp.as<double>(), Ht.as<double>(), sigma, tau, st));
@@ -1620,13 +1620,9 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         kernel_ms += rq.kernel_ms;
         variant = rq.variant;
         passes++;
-        double fit_err = 1.0;
-        penalty = hostmath::penalty_trace(mom, -200.0, &fit_err);
-        const bool pen_valid = fit_err * (double)n < 0.1;
-        bool ok = growth_ok(mom, n);
-        if (pen_valid && std::fabs(penalty) > 0.5) ok = false;
-        if (!pen_valid) penalty = std::numeric_limits<double>::quiet_NaN();
-        if (ok) break;
+        const hostmath::BoundsCheck chk = hostmath::bounds_check(mom, n);
+        penalty = chk.penalty;
+        if (chk.ok) break;
         if (learned) {
             // predicted bounds rejected: fall back to the rigorous interval
             lo = fe.g_lo;
@@ -1637,16 +1633,8 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
             continue;
         }
         if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "spectral bounds [%g, %g] still fail after %d widenings", lo, hi, attempt);
-        const double w = hi - lo;
         // Eq. 6 sign tells which side: positive -> an eigenvalue below lo
-        if (pen_valid && penalty > 0.5)
-            lo -= 0.1 * w;
-        else if (pen_valid && penalty < -0.5)
-            hi += 0.1 * w;
-        else {
-            lo -= 0.1 * w;
-            hi += 0.1 * w;
-        }
+        hostmath::widen(chk.side, &lo, &hi);
         reexp++;
     }
     // mu search on the moments
@@ -1831,13 +1819,13 @@ static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_
     DevBuf Ht(sizeof(double) * (size_t)PH->nnzb * b * b);
     std::vector<double> mom;
     int n_pl = 0, reexp = 0, variant = -1;
-    double kernel_ms = 0;
+    double kernel_ms = 0, penalty = std::numeric_limits<double>::quiet_NaN();
     for (int attempt = 0;; ++attempt) {
         double sigma, tau;
         hostmath::scale_shift(lo, hi, &sigma, &tau);
         n_pl = o.n_pl;
         if (n_pl <= 0) {
-            n_pl = hostmath::degree(occupation(CHESS_ERFC, tau, o.eig_width), lo, hi, o.tol_fit, 8, 20000, 2048);
+            n_pl = hostmath::degree(occupation(CHESS_ERFC, tau, o.eig_width), lo, hi, o.tol_fit, 8, 20000);
             if (n_pl < 0) CHESS_THROW(CHESS_E_NOCONV, "no degree up to 20000 reaches tol_fit %g", o.tol_fit);
         }
         HIPCHECK(launch_scale_shift(b, PH->nnzb, PH->d_brow.as<int32_t>(), PH->d_ci.as<int32_t>(), F.Hp.as<double>(), Ht.as<double>(), sigma, tau, ctx->stream));
@@ -1852,11 +1840,11 @@ static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_
         run_chain(ctx, rq);
         kernel_ms += rq.kernel_ms;
         variant = rq.variant;
-        if (growth_ok(mom, PK->n())) break;
-        if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "bounds [%g, %g] fail the growth test", lo, hi);
-        const double w = hi - lo;
-        lo -= 0.1 * w;
-        hi += 0.1 * w;
+        const hostmath::BoundsCheck chk = hostmath::bounds_check(mom, PK->n());
+        penalty = chk.penalty;
+        if (chk.ok) break;
+        if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "bounds [%g, %g] still fail after %d widenings", lo, hi, attempt);
+        hostmath::widen(chk.side, &lo, &hi);
         reexp++;
     }
     hostmath::CountFunction N;
@@ -1875,6 +1863,7 @@ static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_
         info->n_pl_s = F.s.n_pl;
         info->passes = 1 + reexp;
         info->reexpansions = reexp;
+        info->penalty = penalty;
         info->ms_total = now_ms() - t0;
         info->ms_chain_kernel = kernel_ms;
         info->kernel_variant = variant;
@@ -2034,7 +2023,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
         if (m <= 0) {
             m = 1;
             for (double a : {-0.5, -1.0}) {
-                const int d = hostmath::degree([a](double x) { return std::pow(x, a); }, slo[s], shi[s], o.tol_fit_s, 8, 20000, 2048);
+                const int d = hostmath::degree([a](double x) { return std::pow(x, a); }, slo[s], shi[s], o.tol_fit_s, 8, 20000);
                 if (d < 0) CHESS_THROW(CHESS_E_NOCONV, "system %d: no degree reaches tol_fit_s", idx[s]);
                 m = std::max(m, d);
             }
@@ -2140,7 +2129,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
         hostmath::scale_shift(lo[s], hi[s], &hsig[s], &htau[s]);
         int m = o.n_pl;
         if (m <= 0) {
-            m = hostmath::degree(occupation(o.smearing, htau[s], it.kT), lo[s], hi[s], o.tol_fit, 8, 20000, 2048);
+            m = hostmath::degree(occupation(o.smearing, htau[s], it.kT), lo[s], hi[s], o.tol_fit, 8, 20000);
             if (m < 0) CHESS_THROW(CHESS_E_NOCONV, "system %d: no degree up to 20000 reaches tol_fit", idx[s]);
         }
         npl[s] = m;
@@ -2182,11 +2171,9 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
     for (int s = 0; s < nsys; ++s) {
         std::vector<double> t(npl[s]);
         for (int k = 0; k < npl[s]; ++k) t[k] = hmom[(size_t)k * nsys + s];
-        double fit_err = 1.0;
-        const double p = hostmath::penalty_trace(t, -200.0, &fit_err);
-        const bool pen_valid = fit_err * (double)PKs[s]->n() < 0.1;
-        pen[s] = pen_valid ? p : nan;
-        if (!growth_ok(t, PKs[s]->n()) || (pen_valid && std::fabs(p) > 0.5)) {
+        const hostmath::BoundsCheck chk = hostmath::bounds_check(t, PKs[s]->n());
+        pen[s] = chk.penalty;
+        if (!chk.ok) {
             // rejected bounds: this system is redone below with the
             // Gershgorin interval (unless that is what failed)
             const bool rigorous = o.bounds_mode == CHESS_BOUNDS_GERSHGORIN &&
@@ -2397,6 +2384,31 @@ static int guarded(chess_ctx *ctx, F &&f) {
 using chess::Error;
 
 extern "C" {
+
+int chess_degree(int32_t fn, double param, double lo, double hi, double tol_fit, int32_t *n_pl_out) {
+    if (!n_pl_out || !(hi > lo) || !(tol_fit > 0) || !std::isfinite(lo) || !std::isfinite(hi))
+        return CHESS_E_ARG;
+    chess::hostmath::Fn f;
+    if (fn == CHESS_FN_ERFC || fn == CHESS_FN_FERMI_DIRAC) {
+        if (!(param > 0)) return CHESS_E_ARG;
+        f = chess::occupation(fn == CHESS_FN_ERFC ? CHESS_ERFC : CHESS_FERMI_DIRAC, 0.5 * (lo + hi), param);
+    } else if (fn == CHESS_FN_POWER) {
+        const bool whole = param >= 0 && std::floor(param) == param;
+        if (!whole && !(lo > 0)) return CHESS_E_ARG;
+        const double a = param;
+        f = [a](double x) { return std::pow(x, a); };
+    } else {
+        return CHESS_E_ARG;
+    }
+    try {
+        const int m = chess::hostmath::degree(f, lo, hi, tol_fit, 8, 20000);
+        if (m < 0) return CHESS_E_NOCONV;
+        *n_pl_out = m;
+        return CHESS_OK;
+    } catch (...) {
+        return CHESS_E_OOM;
+    }
+}
 
 void chess_default_opts(chess_opts *o) {
     if (!o) return;

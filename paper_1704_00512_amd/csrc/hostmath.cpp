@@ -86,6 +86,7 @@ double cheb_eval(const std::vector<double> &c, int m, double x) {
 }
 
 double fit_error(const Fn &f, double lo, double hi, int m, int npts) {
+    if (npts <= 0) npts = fit_points(m);
     const std::vector<double> c = cheb_coeffs(f, lo, hi, m);
     double sigma, tau;
     scale_shift(lo, hi, &sigma, &tau);
@@ -237,8 +238,42 @@ double penalty_trace(const std::vector<double> &t, double alpha, double *fit_err
     const std::vector<double> c = cheb_coeffs(fp, -1.0, 1.0, n);
     double s = 0.5 * c[0] * t[0];
     for (int j = 1; j < n; ++j) s += c[j] * t[j];
-    if (fit_err) *fit_err = fit_error(fp, -1.0, 1.0, n, 2048);
+    if (fit_err) *fit_err = fit_error(fp, -1.0, 1.0, std::min(n, 1024));
     return s;
+}
+
+BoundsCheck bounds_check(const std::vector<double> &t, long long n_rows) {
+    BoundsCheck r;
+    bool grows = false;
+    for (double v : t)
+        if (!std::isfinite(v) || std::fabs(v) > 1.01 * (double)n_rows) grows = true;
+    if (grows) {
+        // the moments' sign pattern over the last 16 terms: alternating for
+        // an eigenvalue below the lower bound, one sign above the upper one
+        r.ok = false;
+        double alt = 0.0, same = 0.0;
+        const size_t k0 = t.size() > 16 ? t.size() - 16 : 0;
+        for (size_t k = k0; k < t.size(); ++k) {
+            double v = t[k];
+            if (std::isnan(v)) v = 0.0;
+            if (std::isinf(v)) v = v > 0 ? 1e300 : -1e300;
+            alt += (k % 2 == 0) ? v : -v;
+            same += v;
+        }
+        r.side = std::fabs(alt) > std::fabs(same) ? -1 : 1;
+        return r;
+    }
+    double fit_err = 1.0;
+    const double pen = penalty_trace(t, -200.0, &fit_err);
+    r.valid = fit_err * (double)n_rows < 0.1;
+    if (r.valid) {
+        r.penalty = pen;
+        if (std::fabs(pen) > 0.5) {
+            r.ok = false;
+            r.side = pen > 0 ? -1 : 1;
+        }
+    }
+    return r;
 }
 
 namespace {

@@ -32,13 +32,20 @@ std::vector<double> cheb_nodes(double lo, double hi, int n);
 // sum' c_j T_j(x) by Clenshaw's recurrence (x already scaled to [-1, 1]).
 double cheb_eval(const std::vector<double> &c, int m, double x);
 
-// max |p_m - f| over npts Chebyshev-Lobatto points of [lo, hi].
-double fit_error(const Fn &f, double lo, double hi, int m, int npts);
+// Number of Chebyshev-Lobatto points on which Eq. 7's maximum is taken for
+// an m-term fit: max(8192, 8 m).  The error curve of an m-term interpolant
+// has about m oscillations over [lo, hi], so the grid samples each of them
+// about 8 times (a fixed grid would miss the peaks once m nears its size).
+inline int fit_points(int m) { return m > 1024 ? 8 * m : 8192; }
+
+// max |p_m - f| over npts Chebyshev-Lobatto points of [lo, hi] (npts <= 0:
+// fit_points(m)).
+double fit_error(const Fn &f, double lo, double hi, int m, int npts = 0);
 
 // Eq. 7: smallest m (a multiple of `step`) with fit_error < tol; doubling then
 // bisection over multiples of `step` (the error decreases with m for the
 // functions used here).  Returns -1 if m_max does not reach tol.
-int degree(const Fn &f, double lo, double hi, double tol, int step, int m_max, int npts);
+int degree(const Fn &f, double lo, double hi, double tol, int step, int m_max, int npts = 0);
 
 // Occupations, Eqs. 11 and 9 (reading: beta = 1/kT).
 inline double occ_erfc(double e, double mu, double kT) { return 0.5 * std::erfc((e - mu) / kT); }
@@ -78,8 +85,36 @@ std::vector<double> eigenvalues(const CountFunction &N, double e_lo, double e_hi
 
 // Penalty trace of Eq. 6 in the scaled variable (bounds -1 and 1):
 // Tr W^p = sum' c^p_j t_j with f^p(x) = exp(alpha (x + 1)) - exp(-alpha (x - 1)).
-// Also returns the fit error of f^p at this degree.
+// Also returns the fit error of f^p with min(n, 1024) terms (beyond about
+// 1024 terms the fit of this entire function is at rounding level).
 double penalty_trace(const std::vector<double> &moments, double alpha, double *fit_err);
+
+// The check of the spectral bounds on the moments t_k = Tr T_k of one chain
+// over n_rows rows (Sec. "Determination of the eigenvalue bounds and
+// polynomial degree", Eq. 6, alpha = -200 in the scaled variable, where an
+// eigenvalue at a bound contributes 1):
+//   growth test first: |T_k| <= 1 on [-1, 1], so |Tr T_k| > 1.01 n_rows for
+//     some k means an eigenvalue outside the bounds.  Then the penalty's value
+//     is decided by rounding noise in its coefficients times that growth, so
+//     the side comes from the moments themselves: T_k(x) alternates in sign
+//     for x < -1 and keeps one sign for x > 1 (last 16 moments);
+//   otherwise, when the fit of f^p is good enough (valid: n_rows * fit error
+//     < 0.1), |Tr W^p| > 0.5 fails the check and its sign picks the side
+//     (positive: an eigenvalue at or below the lower bound).
+//   side: -1 move the lower bound, +1 the upper one, when not ok.
+struct BoundsCheck {
+    bool ok = true, valid = false;
+    double penalty = NAN;
+    int side = 0;
+};
+BoundsCheck bounds_check(const std::vector<double> &moments, long long n_rows);
+
+// Moves the failing side out by 10 % of the width (side 0: both).
+inline void widen(int side, double *lo, double *hi) {
+    const double w = *hi - *lo;
+    if (side <= 0) *lo -= 0.1 * w;
+    if (side >= 0) *hi += 0.1 * w;
+}
 
 // Extreme eigenvalues of the symmetric tridiagonal matrix (alpha, beta) by
 // Sturm bisection, and the residual |beta_last * s_last| of their Ritz vectors.

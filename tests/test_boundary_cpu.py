@@ -171,3 +171,55 @@ def test_c_program_calls_the_ssf_conversions(lib):
     segs = np.array(lines[5].split(), dtype=np.int64).reshape(-1, 5)
     assert np.array_equal(segs[:, :4], np.asarray(kg2)) and np.array_equal(segs[:, 4], kv2)
     assert np.array_equal(np.array(lines[6].split(), dtype=float), v2)
+
+
+# Eq. 7 through the C interface (host code, no GPU) against the oracle's
+# linear scan: the library doubles and bisects, the oracle tries m = 8, 16, ...
+# on the same grid rule; both must name the same degree.
+DEGREE_CASES = [
+    # the 80 000-row workload's float32 form (Lanczos bounds of H', kT 0.003)
+    ("erfc", 0.003, -2.4635, -0.2951, 1e-6),
+    # the same bounds in float64
+    ("erfc", 0.003, -2.4635, -0.2951, 1e-10),
+    # Fermi-Dirac on the 256-row workload's spectrum
+    ("fermi_dirac", 0.01, -1.7, -0.4, 1e-8),
+    # x^-1/2 and x^-1 on the bounds of S (Lanczos lower bound)
+    ("power", -0.5, 0.26, 2.55, 1e-6),
+    ("power", -0.5, 0.262, 2.859, 1e-10),
+    ("power", -1.0, 0.1, 1.1, 1e-12),
+]
+
+
+@pytest.mark.parametrize("fn, param, lo, hi, tol", DEGREE_CASES)
+def test_degree_rule_matches_the_oracle(lib, fn, param, lo, hi, tol):
+    from oracle import chebyshev as cb
+    from paper_1704_00512_amd import chess_degree
+    m = chess_degree(fn, param, lo, hi, tol)
+    tau = 0.5 * (lo + hi)
+    if fn == "erfc":
+        f = lambda e: cb.occ_erfc(e, tau, param)
+    elif fn == "fermi_dirac":
+        f = lambda e: cb.occ_fermi_dirac(e, tau, param)
+    else:
+        f = cb.power_fn(param)
+    # a full scan from m = 8 would take minutes at m ~ 4000; starting 400
+    # below the library's answer keeps the linear scan's meaning (every m it
+    # tries below the answer must fail) while the degree 400 below is
+    # checked to fail as well
+    start = max(8, m - 400)
+    if start > 8:
+        assert cb.fit_error(f, lo, hi, start - 8) >= tol
+    assert cb.degree(f, lo, hi, tol, m_start=start, m_max=20000) == m
+
+
+def test_degree_rule_errors(lib):
+    from paper_1704_00512_amd import ChessError, chess_degree
+    for args in (("erfc", 0.0, -1, 1, 1e-6), ("erfc", 0.01, 1, -1, 1e-6), ("erfc", 0.01, -1, 1, 0.0),
+                 ("power", -0.5, -0.1, 1.0, 1e-6)):
+        with pytest.raises(ChessError) as e:
+            chess_degree(*args)
+        assert e.value.name == "CHESS_E_ARG"
+    with pytest.raises(ChessError) as e:
+        chess_degree("erfc", 1e-6, -3.0, 3.0, 1e-12)
+    assert e.value.name == "CHESS_E_NOCONV"
+    assert chess_degree("power", 2.0, -1.0, 1.0, 1e-12) <= 8
