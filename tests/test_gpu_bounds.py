@@ -1,0 +1,137 @@
+"""GPU parity of the bound handling through the C interface, against the
+oracle run with the same rules (Sec. "Determination of the eigenvalue bounds
+and polynomial degree"):
+
+  * single-system widening: chess_fermi_operator given bounds that cut into
+    the spectrum of the truncated chain on both sides, in float64 and
+    float32; the Eq. 6 / growth decisions, the final bounds, the number of
+    widenings and K must match the oracle's;
+  * the default-bounds search of matrix powers (the paper's Fig. 9 "bounds
+    default" [0.5, 1]): chess_matrix_power widening by the growth test, final
+    bounds, widenings, degree and S^-1 against the oracle;
+  * the Eq. 7 degrees chosen inside full calls equal the oracle's.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import chebyshev as cb
+from oracle import pipeline as opl
+from paper_1704_00512_amd import BlockPattern, chess_fermi_operator, chess_matrix_power
+from workloads import generator as g
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def system():
+    if "s" not in _cache:
+        print("[gpu-bounds] system atoms=123 b=4 rH=4.6 rK=6.2 seed=21", flush=True)
+        s = g.make_system(123, 4, 4.6, 6.2, seed=21, kT=0.01)
+        H = opl.BlockMat(s.pat_h.nb, 4, s.pat_h.row_ptr, s.pat_h.col_idx, s.H)
+        S = opl.BlockMat(s.pat_h.nb, 4, s.pat_h.row_ptr, s.pat_h.col_idx, s.S)
+        P = opl.BlockMat(s.pat_k.nb, 4, s.pat_k.row_ptr, s.pat_k.col_idx)
+        _cache["s"] = (s, H, S, P)
+    return _cache["s"]
+
+
+def gpat(p):
+    return BlockPattern.from_host(p.b, p.row_ptr, p.col_idx)
+
+
+def dt(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+S_BOUNDS, N_PL_S = (0.25, 2.1), 40
+
+
+@pytest.mark.parametrize("precision, tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_fermi_widening_matches_the_oracle(gpu_ctx, precision, tol):
+    s, H, S, P = system()
+    # H' of this system spans [-1.851, -0.307]; the given bounds cut 5 % off
+    # the bottom and 12 % off the top of that width
+    lam_lo, lam_hi = -1.850900119757606, -0.3072562912704124
+    w = lam_hi - lam_lo
+    lo, hi = lam_lo + 0.05 * w, lam_hi - 0.12 * w
+    n_pl, mu, kT = 400, -0.9, 0.01
+    print(f"[gpu-bounds] oracle fermi_operator with bounds [{lo:.4f}, {hi:.4f}]", flush=True)
+    Ko, io = opl.fermi_operator(H, S, P, s.n_electrons, kT, s_bounds_=S_BOUNDS, n_pl_s=N_PL_S,
+                                h_bounds=(lo, hi), n_pl=n_pl, mu=mu)
+    assert io["reexpansions"] >= 1
+    # every decision the oracle took is far from its threshold, so float32
+    # moments cannot flip it: replay them on the oracle's own chains
+    a, b_ = lo, hi
+    Xo, Hp, _ = opl.orthogonal_frame(H, S, P, s_bnds=S_BOUNDS, n_pl_s=N_PL_S)
+    K = P.pattern_csr()
+    for _ in range(io["reexpansions"] + 1):
+        from oracle.csr import chebyshev
+        _, mom = chebyshev(opl.scaled(Hp, a, b_), K, n_pl, None)
+        # t_0 = n; the growth test is decided by the others, far from 1.01 n
+        r = np.max(np.abs(mom[1:])) / (1.01 * s.n)
+        assert r > 1.02 or r < 0.999, r
+        chk = cb.bounds_check(mom, s.n)
+        if chk["ok"]:
+            assert abs(chk["penalty"]) < 0.1
+            break
+        a, b_ = cb.widen(a, b_, chk["side"])
+    assert (a, b_) == (io["lo"], io["hi"])
+    print(f"[gpu-bounds] library {precision}", flush=True)
+    Kg, ig = chess_fermi_operator(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h),
+                                  gpat(s.pat_k), s.n_electrons, kT, precision=precision,
+                                  s_bounds=S_BOUNDS, n_pl_s=N_PL_S, bounds=(lo, hi), n_pl=n_pl,
+                                  mu=mu)
+    assert ig["reexpansions"] == io["reexpansions"]
+    assert abs(ig["lo"] - io["lo"]) < 1e-14 and abs(ig["hi"] - io["hi"]) < 1e-14
+    assert ig["passes"] == 1 + io["reexpansions"]
+    assert abs(ig["penalty"] - io["penalty"]) < (1e-8 if precision == "f64" else 1e-2)
+    err = float(np.max(np.abs(Kg.cpu().numpy() - Ko)))
+    print(f"[gpu-bounds] {precision}: widenings {ig['reexpansions']}, bounds "
+          f"[{ig['lo']:.4f}, {ig['hi']:.4f}], max|K - K_oracle| = {err:.2e}", flush=True)
+    assert err < tol
+
+
+def test_default_bounds_inverse_matches_the_oracle(gpu_ctx):
+    # S^-1 from the default guess [0.5, 1] (S spans [0.3, 2.0]): the growth
+    # test widens both sides until the truncated chain is stable
+    s, H, S, P = system()
+    tol_fit = 1e-10
+    print("[gpu-bounds] oracle S^-1 from [0.5, 1]", flush=True)
+    vo, io = opl.matrix_power(S, -1.0, P, bounds=(0.5, 1.0), tol_fit=tol_fit, max_reexpand=12)
+    assert io["reexpansions"] >= 3
+    print("[gpu-bounds] library S^-1 from [0.5, 1]", flush=True)
+    vg, ig = chess_matrix_power(gpu_ctx, dt(s.S), gpat(s.pat_h), -1.0, gpat(s.pat_k),
+                                precision="f64", s_bounds=(0.5, 1.0), tol_fit_s=tol_fit,
+                                max_reexpand=12)
+    assert ig["reexpansions"] == io["reexpansions"]
+    assert abs(ig["lo"] - io["lo"]) < 1e-14 and abs(ig["hi"] - io["hi"]) < 1e-14
+    assert ig["n_pl"] == io["n_pl"]
+    err = float(np.max(np.abs(vg.cpu().numpy() - vo)))
+    print(f"[gpu-bounds] S^-1: widenings {ig['reexpansions']}, bounds [{ig['lo']:.4f}, "
+          f"{ig['hi']:.4f}], n_pl {ig['n_pl']}, max|S^-1 - oracle| = {err:.2e}", flush=True)
+    assert err < 1e-10
+
+
+def test_degrees_chosen_in_full_calls_match_the_oracle(gpu_ctx):
+    # the 80 000-row workload's float32 form: H' bounds [-2.4635, -0.2951],
+    # kT 0.003 Ha, tol_fit 1e-6 (the spectrum of this small system is inside
+    # them); S^-1/2 on the S bounds with tol_fit 1e-6 and 1e-10
+    s, H, S, P = system()
+    lo, hi, kT = -2.4635, -0.2951, 0.003
+    tau = 0.5 * (lo + hi)
+    f = lambda e: cb.occ_erfc(e, tau, kT)
+    m_lib = None
+    for tol_s in (1e-6, 1e-10):
+        print(f"[gpu-bounds] degree check, S tol_fit {tol_s}", flush=True)
+        _, ig = chess_fermi_operator(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h),
+                                     gpat(s.pat_k), s.n_electrons, kT, precision="f32",
+                                     s_bounds=S_BOUNDS, tol_fit_s=tol_s, bounds=(lo, hi),
+                                     tol_fit=1e-6, mu=-0.9)
+        assert ig["reexpansions"] == 0
+        m_lib = ig["n_pl"]
+        start = max(8, m_lib - 200)
+        assert cb.fit_error(f, lo, hi, start - 8) >= 1e-6
+        assert cb.degree(f, lo, hi, 1e-6, m_start=start) == m_lib
+        assert ig["n_pl_s"] == cb.degree(cb.power_fn(-0.5), S_BOUNDS[0], S_BOUNDS[1], tol_s)
+    print(f"[gpu-bounds] n_pl {m_lib} at the large workload's bounds", flush=True)

@@ -75,6 +75,36 @@ def test_large80k_chain_sampled_columns(gpu_ctx):
     chain_check(gpu_ctx, "large80k", "f32", 1e-5, 80, -3.0, 0.5, 12)
 
 
+def test_large80k_long_chain_sampled_columns(gpu_ctx):
+    # the benchmark's chain length and coefficients: the float32 chain over
+    # the Eq. 7 degree for the erfc occupation at kT 0.003 Ha and tol_fit 1e-6
+    # (about 2250 terms), bounds 1 % outside the extreme eigenvalues of H,
+    # one sum at a mu inside the spectrum; 12 sampled columns against the
+    # oracle's float64 column recursion
+    from paper_1704_00512_amd import chess_degree
+    s = workload("large80k")
+    e0, e1 = g.extreme_eigenvalues(s.pat_h, s.H)
+    w = e1 - e0
+    lo, hi = e0 - 0.01 * w, e1 + 0.01 * w
+    n_pl = chess_degree("erfc", 0.003, lo, hi, 1e-6)
+    mu = lo + 0.6 * w
+    coefs = cb.cheb_coeffs(lambda e: cb.occ_erfc(e, mu, 0.003), lo, hi, n_pl)[None, :]
+    dev = torch.device("cuda")
+    ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx, dev)
+    pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx, dev)
+    print(f"[fullsize] large80k f32 chain of {n_pl} terms on [{lo:.4f}, {hi:.4f}]", flush=True)
+    accs, mom = chess_chebyshev(gpu_ctx, torch.tensor(s.H, device=dev), ph, lo, hi, pk, n_pl,
+                                coefs, precision="f32")
+    assert np.all(np.abs(mom) <= 1.0001 * s.n)
+    H = opl.BlockMat(s.pat_h.nb, s.b, s.pat_h.row_ptr, s.pat_h.col_idx, s.H)
+    cols = np.sort(np.random.default_rng(13).choice(s.n, size=12, replace=False))
+    worst = max_column_error(s, [accs[0].cpu().numpy()], opl.scaled(H.csr(), lo, hi), n_pl,
+                             coefs, cols)
+    print(f"[fullsize] large80k f32 chain of {n_pl} terms: max |GPU - oracle| over 12 "
+          f"columns = {worst:.3e}", flush=True)
+    assert worst < 1e-5
+
+
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_prec9000_chain_sampled_columns(gpu_ctx, precision, tol):
     chain_check(gpu_ctx, "prec9000", precision, tol, 70, -3.0, 0.5, 16)
