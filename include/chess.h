@@ -59,10 +59,21 @@ enum {
     CHESS_E_CAPACITY = -9     /* eigenvalue buffer too small; *n_found holds the count */
 };
 
-/* Precision of the Chebyshev chain.  Inputs and outputs are always float64;
- * CHESS_F32 runs the products in float32 while the weighted sums of Eq. 1,
- * the traces and the bound/mu logic stay in float64. */
-enum { CHESS_F64 = 0, CHESS_F32 = 1 };
+/* Precision of the Chebyshev chain.  Inputs and outputs are always float64,
+ * and so are the weighted sums of Eq. 1, the traces and the bound/mu logic.
+ *   CHESS_F64    : float64 chain;
+ *   CHESS_F32    : T_k stored and multiplied in float32;
+ *   CHESS_BF16   : T_k stored in float32, each product's operands rounded to
+ *                  bfloat16 (nearest even), float32 accumulation on the
+ *                  matrix cores (block edge 4 only);
+ *   CHESS_BF16X3 : T_k in float32, each operand x split as hi = bf16(x),
+ *                  lo = bf16(x - hi) and the product taken as
+ *                  hi*hi + hi*lo + lo*hi, float32 accumulation (block edge
+ *                  4 only).
+ * Default Eq. 7 thresholds: 1e-10 (F64), 1e-6 (F32, BF16X3), 1e-4 (BF16).
+ * The bfloat16 forms return CHESS_E_UNSUPPORTED for b = 9 or rows of more
+ * than 254 blocks. */
+enum { CHESS_F64 = 0, CHESS_F32 = 1, CHESS_BF16 = 2, CHESS_BF16X3 = 3 };
 
 /* Occupation function for the Fermi-operator expansion. */
 enum {
@@ -97,7 +108,7 @@ typedef struct {
 } chess_matrix;
 
 typedef struct {
-    int32_t precision;   /* CHESS_F64 or CHESS_F32 (default CHESS_F32) */
+    int32_t precision;   /* CHESS_F64, CHESS_F32 (default), CHESS_BF16 or CHESS_BF16X3 */
     int32_t smearing;    /* CHESS_ERFC (default) or CHESS_FERMI_DIRAC */
     int32_t bounds_mode; /* for bounds not given (default CHESS_BOUNDS_GERSHGORIN) */
     int32_t n_pl;        /* > 0: fixed number of terms for H (or M); 0: Eq. 7 */
@@ -106,7 +117,7 @@ typedef struct {
                                 mu search (one chain pass); 0: second pass at the final mu */
     int32_t max_reexpand;    /* widenings allowed when Eq. 6 or the growth test fails (3) */
     int32_t lanczos_steps;   /* Lanczos steps for CHESS_BOUNDS_LANCZOS and for S (40) */
-    double tol_fit;      /* Eq. 7 threshold for H (<= 0: 1e-10 for F64, 1e-6 for F32) */
+    double tol_fit;      /* Eq. 7 threshold for H (<= 0: by precision, see above) */
     double tol_fit_s;    /* Eq. 7 threshold for x^-1/2 or x^a (<= 0: same rule) */
     double tol_ne;       /* |N(mu) - N_e| target of the mu search (<= 0: 1e-8 N_e) */
     double bounds[2];    /* spectral bounds of H' = S^-1/2 H S^-1/2 (or of M); NaN = estimate */

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchess.so")
 
 CHESS_OK = 0
-CHESS_F64, CHESS_F32 = 0, 1
+CHESS_F64, CHESS_F32, CHESS_BF16, CHESS_BF16X3 = 0, 1, 2, 3
 CHESS_ERFC, CHESS_FERMI_DIRAC = 0, 1
 CHESS_BOUNDS_GERSHGORIN, CHESS_BOUNDS_LANCZOS = 0, 1
 CHESS_FN_ERFC, CHESS_FN_FERMI_DIRAC, CHESS_FN_POWER = 0, 1, 2

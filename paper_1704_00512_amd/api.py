@@ -89,7 +89,8 @@ def default_opts(**kw) -> _lib.chess_opts:
         elif k == "mu":
             o.mu = math.nan if v is None else float(v)
         elif k == "precision" and isinstance(v, str):
-            o.precision = {"f64": _lib.CHESS_F64, "f32": _lib.CHESS_F32}[v]
+            o.precision = {"f64": _lib.CHESS_F64, "f32": _lib.CHESS_F32, "bf16": _lib.CHESS_BF16,
+                           "bf16x3": _lib.CHESS_BF16X3}[v]
         elif k == "smearing" and isinstance(v, str):
             o.smearing = {"erfc": _lib.CHESS_ERFC, "fermi_dirac": _lib.CHESS_FERMI_DIRAC}[v]
         elif k in ("sinvhalf_in", "sinvhalf_out"):

@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _CSRC = os.path.join(_HERE, "csrc")
-SOURCES = ["kernels.hip", "kernels_listed.hip", "kernels_bf16.hip", "learned.hip", "chess.cpp",
+SOURCES = ["kernels.hip", "kernels_listed.hip", "kernels_stat.hip", "learned.hip", "chess.cpp",
            "hostmath.cpp", "ssf.cpp"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -141,11 +141,12 @@ struct ListedPlan {
     const Pattern *a = nullptr, *bt = nullptr, *c = nullptr;
     int dtype = 0;
     bool usable = false;  // false: rows too long for the list format
-    int tuned_variant = -1;  // fastest kernel variant on this plan (-1: not timed yet)
+    int tuned_variant[3] = {-1, -1, -1};  // fastest kernel variant per operand mode (-1: not timed yet)
     std::vector<int32_t> breaks;     // rows where a tile must start (batches: system starts)
     std::vector<int32_t> tile_row0;  // host copy, ntiles + 1
     ListedPlanDev dev;
     DevBuf d_tile_row0, d_j_off, d_j_rec, d_entries, d_lean_rec, d_lean_ent;
+    DevBuf d_st_goff, d_st_ginfo, d_st_slot, d_st_list;  // output-stationary groups
 };
 
 // Learned bound / mu predictor loaded by chess_model_load (layout of the
@@ -274,6 +275,14 @@ static int pick_cmax(int dtype, int b) {
     return dtype == 1 ? 2 : 1;
 }
 
+// Chain storage precision (0 = float64, 1 = float32) and operand mode of the
+// products (kernels.h) for an opts precision: the bfloat16 forms keep T_k in
+// float32 and round only the product operands.
+static int storage_dtype(int precision) { return precision == CHESS_F64 ? 0 : 1; }
+static int operand_mode(int precision) {
+    return precision == CHESS_BF16 ? kStatBF16 : precision == CHESS_BF16X3 ? kStatBF16X3 : 0;
+}
+
 // Symbolic plan of C = P_C o (A Bt^T) (see kernels.h).
 static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Pattern *Bt,
                                    const Pattern *C, int dtype) {
@@ -390,6 +399,152 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
     if (lds > 160 * 1024) CHESS_THROW(CHESS_E_UNSUPPORTED, "product tile needs %zu bytes of LDS", lds);
     ctx->plans.push_back(std::move(P));
     return ctx->plans.back().get();
+}
+
+// Output-stationary groups of a listed plan (kernels_stat.hip; b = 4): per
+// tile, the output blocks sorted by hit count (descending; ties in row-major
+// order) and cut into groups of G = 16 (float32 storage) or 4 (float64); a
+// group runs R rounds, its largest hit count rounded up to 8; each slot's
+// list holds its hits (position in A row i, position in Bt row j) in the
+// order of l, then the row's zero block.  Leaves the plan without groups when
+// a row is too long for one-byte positions or the packed fields overflow.
+static void build_stat_groups(chess_ctx *ctx, ListedPlan *P) {
+    const Pattern *A = P->a, *Bt = P->bt, *C = P->c;
+    if (A->b != 4 || A->max_row > 254 || Bt->max_row > 255 || Bt->nnzb >= ((int64_t)1 << 22) ||
+        C->nnzb >= ((int64_t)1 << 32) - 1)
+        return;
+    const int G = P->dtype == 0 ? 4 : 16;
+    const std::vector<int32_t> &tr0 = P->tile_row0;
+    const int ntiles = (int)tr0.size() - 1;
+    struct TileOut {
+        std::vector<int32_t> ginfo;   // 2 per group (list offset relative to the tile)
+        std::vector<uint32_t> slot;   // 2 per slot
+        std::vector<uint16_t> list;   // entries, 8 per 16-byte unit
+        int ablocks = 0;
+        bool overflow = false;
+    };
+    std::vector<TileOut> outs(ntiles);
+    auto work = [&](int t0, int t1) {
+        std::vector<uint16_t> ent;
+        struct Out { uint32_t blk; int row; int64_t first; int n; int32_t j; };
+        std::vector<Out> o;
+        for (int t = t0; t < t1; ++t) {
+            TileOut &to = outs[t];
+            const int row0 = tr0[t], c = tr0[t + 1] - row0;
+            int ab[4] = {0, 0, 0, 0}, len[4] = {0, 0, 0, 0};
+            int acc = 0;
+            for (int r = 0; r < c; ++r) {
+                len[r] = (int)(A->rp[row0 + r + 1] - A->rp[row0 + r]);
+                ab[r] = acc;
+                acc += len[r] + 1;
+            }
+            to.ablocks = acc;
+            if (acc >= 1024 || c > 4) {
+                to.overflow = true;
+                continue;
+            }
+            ent.clear();
+            o.clear();
+            for (int r = 0; r < c; ++r) {
+                const int i = row0 + r;
+                for (int64_t q = C->rp[i]; q < C->rp[i + 1]; ++q) {
+                    const int j = C->ci[q];
+                    const int64_t first = (int64_t)ent.size();
+                    int64_t pa = A->rp[i], pe = A->rp[i + 1], pb = Bt->rp[j], be = Bt->rp[j + 1];
+                    while (pa < pe && pb < be) {
+                        const int ca = A->ci[pa], cb = Bt->ci[pb];
+                        if (ca < cb) {
+                            ++pa;
+                        } else if (cb < ca) {
+                            ++pb;
+                        } else {
+                            ent.push_back((uint16_t)((pa - A->rp[i]) | ((pb - Bt->rp[j]) << 8)));
+                            ++pa;
+                            ++pb;
+                        }
+                    }
+                    o.push_back({(uint32_t)q, r, first, (int)((int64_t)ent.size() - first), j});
+                }
+            }
+            std::stable_sort(o.begin(), o.end(), [](const Out &x, const Out &y) { return x.n > y.n; });
+            int64_t list_units = 0;
+            for (size_t g0 = 0; g0 < o.size(); g0 += G) {
+                const size_t g1 = std::min(o.size(), g0 + (size_t)G);
+                const int R = std::max(8, (o[g0].n + 7) & ~7);
+                if (R > 0xFFFF) to.overflow = true;
+                uint32_t dmask = 0;
+                for (size_t k = g0; k < g1; ++k)
+                    if (o[k].j == row0 + o[k].row) dmask |= 1u << (k - g0);
+                to.ginfo.push_back((int32_t)list_units);
+                to.ginfo.push_back((int32_t)(R | (dmask << 16)));
+                for (int sl = 0; sl < G; ++sl) {
+                    const size_t k = g0 + sl;
+                    const bool have = k < g1;
+                    const int r = have ? o[k].row : 0;
+                    const uint32_t bstart = have ? (uint32_t)Bt->rp[o[k].j] : 0u;
+                    to.slot.push_back(have ? o[k].blk : 0xFFFFFFFFu);
+                    to.slot.push_back(bstart | ((uint32_t)ab[r] << 22));
+                    const uint16_t pad = (uint16_t)len[r];  // the row's zero block, Bt position 0
+                    for (int x = 0; x < R; ++x)
+                        to.list.push_back(have && x < o[k].n ? ent[(size_t)o[k].first + x] : pad);
+                }
+                list_units += (int64_t)G * R / 8;
+            }
+        }
+    };
+    const int nthr = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    const int chunk = (ntiles + nthr - 1) / nthr;
+    for (int k = 0; k < nthr; ++k) {
+        const int t0 = k * chunk, t1 = std::min(ntiles, t0 + chunk);
+        if (t0 < t1) pool.emplace_back(work, t0, t1);
+    }
+    for (auto &th : pool) th.join();
+    std::vector<int32_t> goff(ntiles + 1, 0);
+    int64_t ngroups = 0, nunits = 0;
+    int ablocks = 0;
+    for (int t = 0; t < ntiles; ++t) {
+        if (outs[t].overflow) return;
+        goff[t] = (int32_t)ngroups;
+        ngroups += (int64_t)outs[t].ginfo.size() / 2;
+        nunits += (int64_t)outs[t].list.size() / 8;
+        ablocks = std::max(ablocks, outs[t].ablocks);
+    }
+    goff[ntiles] = (int32_t)ngroups;
+    // byte offsets of the lists are 32-bit buffer offsets
+    if (ngroups >= ((int64_t)1 << 31) || (nunits + 2) * 16 >= ((int64_t)1 << 31)) return;
+    std::vector<int32_t> ginfo((size_t)ngroups * 2);
+    std::vector<uint32_t> slot((size_t)ngroups * G * 2);
+    std::vector<uint16_t> list((size_t)nunits * 8);
+    int64_t gbase = 0, ubase = 0;
+    for (int t = 0; t < ntiles; ++t) {
+        TileOut &to = outs[t];
+        const int64_t ng = (int64_t)to.ginfo.size() / 2;
+        for (int64_t g = 0; g < ng; ++g) {
+            ginfo[(size_t)(gbase + g) * 2] = (int32_t)(to.ginfo[(size_t)g * 2] + ubase);
+            ginfo[(size_t)(gbase + g) * 2 + 1] = to.ginfo[(size_t)g * 2 + 1];
+        }
+        std::copy(to.slot.begin(), to.slot.end(), slot.begin() + (size_t)gbase * G * 2);
+        std::copy(to.list.begin(), to.list.end(), list.begin() + (size_t)ubase * 8);
+        gbase += ng;
+        ubase += (int64_t)to.list.size() / 8;
+        std::vector<int32_t>().swap(to.ginfo);
+        std::vector<uint32_t>().swap(to.slot);
+        std::vector<uint16_t>().swap(to.list);
+    }
+    hipStream_t st = ctx->stream;
+    upload(P->d_st_goff, goff, st);
+    upload(P->d_st_ginfo, ginfo, st);
+    upload(P->d_st_slot, slot, st);
+    upload(P->d_st_list, list, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    ListedPlanDev &d = P->dev;
+    d.st_goff = P->d_st_goff.as<int32_t>();
+    d.st_ginfo = P->d_st_ginfo.as<int32_t>();
+    d.st_slot = P->d_st_slot.as<uint32_t>();
+    d.st_list = P->d_st_list.p;
+    d.st_g = G;
+    d.st_ablocks = ablocks;
 }
 
 // Symbolic plan with hit lists for C = P_C o (A Bt^T) (see kernels.h,
@@ -650,6 +805,7 @@ static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Patte
     }
     for (int t = 0; t < ntiles; ++t) d.max_cols = std::max<int>(d.max_cols, (int)(j_off[t + 1] - j_off[t]));
     d.off31 = C->nnzb * b * b * 8 < ((int64_t)1 << 31) && (tot_ent + 1024) * 2 * ew < ((int64_t)1 << 31);
+    if (b == 4 && d.off31) build_stat_groups(ctx, P.get());
     P->usable = listed_product_lds_bytes(dtype, b, d) <= 160 * 1024;
     ctx->lplans.push_back(std::move(P));
     return ctx->lplans.back().get();
@@ -682,8 +838,12 @@ static void product(chess_ctx *ctx, int dtype, const ProductPlan *plan, const vo
 }
 
 static void product_listed(chess_ctx *ctx, int dtype, const ListedPlan *plan, const void *a,
-                           const void *bt, void *c, const Epilogue &ep) {
+                           const void *bt, void *c, const Epilogue &ep, int opmode = 0,
+                           const void *bt_hi = nullptr, const void *bt_lo = nullptr) {
     ProductOperands ops;
+    ops.opmode = opmode;
+    ops.bt_hi = bt_hi;
+    ops.bt_lo = bt_lo;
     ops.a_rp = plan->a->d_rp.as<int64_t>();
     ops.a_val = a;
     ops.bt_rp = plan->bt->d_rp.as<int64_t>();
@@ -809,6 +969,7 @@ struct ChainRequest {
     const double *coef = nullptr;  // host [nq][n_pl]
     double *acc[4] = {nullptr, nullptr, nullptr, nullptr};  // device, float64 on PK (transposed storage)
     int dtype = 0;
+    int opmode = 0;        // operand mode of the products (bfloat16 forms: float32 storage)
     void *hist = nullptr;  // optional device [n_pl][nnzK*b*b] in dtype
     std::vector<double> *moments = nullptr;
     const char *label = "chain";  // stage name given to the progress callback
@@ -822,21 +983,22 @@ struct ChainRequest {
 // launches each, written to a scratch output) and the fastest one is kept for
 // the plan's lifetime.
 static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int n_pl,
-                                  const void *a, const void *bt, const void *prev) {
+                                  const void *a, const void *bt, const void *prev, int opmode = 0,
+                                  const void *bt_hi = nullptr, const void *bt_lo = nullptr) {
     const int b = lp->a->b;
     const int nvar = listed_product_variants(dtype, b, lp->dev);
     if (const char *env = std::getenv("CHESS_LISTED_VARIANT")) {
         char *end = nullptr;
         const long v = std::strtol(env, &end, 10);
-        if (end == env || !listed_product_variant_ok(dtype, b, lp->dev, (int)v))
+        if (end == env || !listed_product_variant_ok(dtype, b, lp->dev, (int)v, opmode))
             CHESS_THROW(CHESS_E_ARG, "CHESS_LISTED_VARIANT=%s: no such kernel variant here (ids 0..%d)", env, nvar - 1);
         lp->dev.variant = (int)v;
-        if (listed_product_lds_bytes(dtype, b, lp->dev) > 160 * 1024)
+        if (listed_product_lds_bytes(dtype, b, lp->dev, opmode) > 160 * 1024)
             CHESS_THROW(CHESS_E_UNSUPPORTED, "kernel variant %ld needs more than 160 KB of LDS", v);
         return;
     }
-    if (lp->tuned_variant >= 0) {
-        lp->dev.variant = lp->tuned_variant;
+    if (lp->tuned_variant[opmode] >= 0) {
+        lp->dev.variant = lp->tuned_variant[opmode];
         return;
     }
     // untimed default: b = 4 float32, the slots shared among the tile rows
@@ -847,9 +1009,13 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
     auto fits = [&](int v) {
         ListedPlanDev d = lp->dev;
         d.variant = v;
-        return listed_product_variant_ok(dtype, b, d, v) && listed_product_lds_bytes(dtype, b, d) <= 160 * 1024;
+        return listed_product_variant_ok(dtype, b, d, v, opmode) && listed_product_lds_bytes(dtype, b, d, opmode) <= 160 * 1024;
     };
-    if (nvar == 1)
+    if (opmode != 0) {
+        if (!fits(kStatVariantF32))
+            CHESS_THROW(CHESS_E_UNSUPPORTED, "bfloat16 operands need b = 4 and rows of at most 254 blocks");
+        lp->dev.variant = kStatVariantF32;
+    } else if (nvar == 1)
         lp->dev.variant = 0;
     else if (b == 4 && dtype == 1)
         lp->dev.variant = fits(20) ? 20 : 8;
@@ -868,27 +1034,31 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
     ops.bt_val = bt;
     ops.c_rp = lp->c->d_rp.as<int64_t>();
     ops.c_out = out.p;
+    ops.opmode = opmode;
+    ops.bt_hi = bt_hi;
+    ops.bt_lo = bt_lo;
     Epilogue ep;
     ep.alpha = 2.0;
     ep.beta = -1.0;
     ep.prev = prev;
     Timer tm(st);
     double best = 0.0;
-    int best_v = 0;
+    int best_v = -1;
     for (int v = 0; v < nvar; ++v) {
         ListedPlanDev d = lp->dev;
         d.variant = v;
-        if (!listed_product_variant_ok(dtype, b, d, v) || listed_product_lds_bytes(dtype, b, d) > 160 * 1024) continue;
+        if (!listed_product_variant_ok(dtype, b, d, v, opmode) || listed_product_lds_bytes(dtype, b, d, opmode) > 160 * 1024) continue;
         HIPCHECK(launch_listed_locked(dtype, b, d, ops, ep, st));
         tm.start();
         for (int r = 0; r < 3; ++r) HIPCHECK(launch_listed_locked(dtype, b, d, ops, ep, st));
         const double ms = tm.stop();
-        if (v == 0 || ms < best) {
+        if (best_v < 0 || ms < best) {
             best = ms;
             best_v = v;
         }
     }
-    lp->tuned_variant = best_v;
+    if (best_v < 0) best_v = lp->dev.variant;
+    lp->tuned_variant[opmode] = best_v;
     lp->dev.variant = best_v;
 }
 
@@ -907,13 +1077,24 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     DevBuf U0(tb), U1(tb), Bt(vbytes(PM, dtype) + 16384);
     // Bt = M~^T on PM (row j of Bt = column j of M~)
     HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, PM->d_tmap.as<int64_t>(), rq.Mt, Bt.p, 1, st));
+    // bfloat16 operand forms of Bt (hi, and lo for the three-product split)
+    DevBuf Bhi, Blo;
+    if (rq.opmode != 0) {
+        if (dtype != 1 || !lplan->usable)
+            CHESS_THROW(CHESS_E_UNSUPPORTED, "bfloat16 operands need b = 4 and rows of at most 254 blocks");
+        const int64_t nv = PM->nnzb * b * b;
+        Bhi.alloc(sizeof(uint16_t) * (size_t)nv + 16384);
+        if (rq.opmode == kStatBF16X3) Blo.alloc(sizeof(uint16_t) * (size_t)nv + 16384);
+        HIPCHECK(launch_split_bf16(nv, Bt.as<float>(), Bhi.as<unsigned short>(),
+                                   rq.opmode == kStatBF16X3 ? Blo.as<unsigned short>() : nullptr, st));
+    }
     // U_0 = I, U_1 = M~^T placed in PK
     HIPCHECK(launch_fill_identity(dtype, b, PK->nnzb, PK->d_brow.as<int32_t>(), PK->d_ci.as<int32_t>(), U0.p, st));
     HIPCHECK(launch_zero(U1.p, tb, st));
     if (rq.n_pl > 1)
         HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, emb->d_map_t.as<int64_t>(), rq.Mt, U1.p, 1, st));
     if (lplan->usable) {
-        select_listed_variant(ctx, lplan, dtype, rq.n_pl, U1.p, Bt.p, U0.p);
+        select_listed_variant(ctx, lplan, dtype, rq.n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p);
         rq.variant = lplan->dev.variant;
     }
     for (int q = 0; q < rq.nq; ++q) {
@@ -954,7 +1135,7 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
         ep.hist = rq.hist ? (char *)rq.hist + (size_t)(k + 1) * tb : nullptr;
         ep.trace_partial = pd + (size_t)(k + 1) * ntiles;
         if (lplan->usable)
-            product_listed(ctx, dtype, lplan, ucur, Bt.p, uprev, ep);
+            product_listed(ctx, dtype, lplan, ucur, Bt.p, uprev, ep, rq.opmode, Bhi.p, Blo.p);
         else
             product(ctx, dtype, plan, ucur, Bt.p, uprev, ep);
         std::swap(ucur, uprev);
@@ -984,6 +1165,7 @@ struct BatchChain {
     const Pattern *PM = nullptr, *PK = nullptr;
     const double *Mt = nullptr;
     int n_pl = 0, nq = 0, dtype = 0;
+    int opmode = 0;  // operand mode of the products (bfloat16 forms: float32 storage)
     const double *coef_tab = nullptr;
     double *acc[4] = {nullptr, nullptr, nullptr, nullptr};
     const std::vector<int32_t> *row0 = nullptr;
@@ -1012,7 +1194,16 @@ static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
     HIPCHECK(launch_fill_identity(dtype, b, PK->nnzb, PK->d_brow.as<int32_t>(), PK->d_ci.as<int32_t>(), U0.p, st));
     HIPCHECK(launch_zero(U1.p, tb, st));
     HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, emb->d_map_t.as<int64_t>(), rq.Mt, U1.p, 1, st));
-    select_listed_variant(ctx, lp, dtype, n_pl, U1.p, Bt.p, U0.p);
+    DevBuf Bhi, Blo;
+    if (rq.opmode != 0) {
+        if (dtype != 1) CHESS_THROW(CHESS_E_UNSUPPORTED, "bfloat16 operands need float32 storage");
+        const int64_t nv = PM->nnzb * b * b;
+        Bhi.alloc(sizeof(uint16_t) * (size_t)nv + 16384);
+        if (rq.opmode == kStatBF16X3) Blo.alloc(sizeof(uint16_t) * (size_t)nv + 16384);
+        HIPCHECK(launch_split_bf16(nv, Bt.as<float>(), Bhi.as<unsigned short>(),
+                                   rq.opmode == kStatBF16X3 ? Blo.as<unsigned short>() : nullptr, st));
+    }
+    select_listed_variant(ctx, lp, dtype, n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p);
     rq.variant = lp->dev.variant;
     DevBuf dcoef(sizeof(double) * (size_t)std::max(rq.nq, 1) * n_pl * nsys);
     if (rq.nq)
@@ -1064,7 +1255,7 @@ static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
             ep.coef_sys[q] = dcoef.as<double>() + ((size_t)q * n_pl + k + 1) * nsys;
         }
         ep.trace_partial = pd + (size_t)(k + 1) * ntiles;
-        product_listed(ctx, dtype, lp, ucur, Bt.p, uprev, ep);
+        product_listed(ctx, dtype, lp, ucur, Bt.p, uprev, ep, rq.opmode, Bhi.p, Blo.p);
         std::swap(ucur, uprev);
     };
     Timer tm(st);
@@ -1120,12 +1311,14 @@ static chess_opts resolve_opts(const chess_opts *o) {
     chess_opts r;
     chess_default_opts(&r);
     if (o) r = *o;
-    if (r.precision != CHESS_F64 && r.precision != CHESS_F32) CHESS_THROW(CHESS_E_UNSUPPORTED, "precision %d", r.precision);
+    if (r.precision != CHESS_F64 && r.precision != CHESS_F32 && r.precision != CHESS_BF16 &&
+        r.precision != CHESS_BF16X3)
+        CHESS_THROW(CHESS_E_UNSUPPORTED, "precision %d", r.precision);
     if (r.smearing != CHESS_ERFC && r.smearing != CHESS_FERMI_DIRAC) CHESS_THROW(CHESS_E_ARG, "smearing %d", r.smearing);
     if (r.bounds_mode != CHESS_BOUNDS_GERSHGORIN && r.bounds_mode != CHESS_BOUNDS_LANCZOS &&
         r.bounds_mode != CHESS_BOUNDS_LEARNED)
         CHESS_THROW(CHESS_E_ARG, "bounds_mode %d", r.bounds_mode);
-    const double deftol = r.precision == CHESS_F64 ? 1e-10 : 1e-6;
+    const double deftol = r.precision == CHESS_F64 ? 1e-10 : r.precision == CHESS_BF16 ? 1e-4 : 1e-6;
     if (!(r.tol_fit > 0)) r.tol_fit = deftol;
     if (!(r.tol_fit_s > 0)) r.tol_fit_s = deftol;
     if (r.max_reexpand < 0) r.max_reexpand = 0;
@@ -1217,7 +1410,8 @@ static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *
         rq.nq = (int)powers.size();
         rq.coef = coef.data();
         for (size_t q = 0; q < powers.size(); ++q) rq.acc[q] = acc[q];
-        rq.dtype = o.precision;
+        rq.dtype = storage_dtype(o.precision);
+        rq.opmode = operand_mode(o.precision);
         rq.moments = &mom;
         run_chain(ctx, rq);
         r.n_pl = n_pl;
@@ -1514,7 +1708,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     Frame F;
     build_frame(ctx, PH, H->val ? (const double *)H->val : nullptr, PS, (const double *)S->val, PK, o, F);
     const int b = PK->b;
-    const int dtype = o.precision;
+    const int dtype = storage_dtype(o.precision);
     const int64_t nK = PK->nnzb * b * b;
     double lo, hi;
     const double nan = std::numeric_limits<double>::quiet_NaN();
@@ -1604,6 +1798,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         rq.PK = PK;
         rq.n_pl = n_pl + extra;
         rq.dtype = dtype;
+        rq.opmode = operand_mode(o.precision);
         rq.moments = &mom;
         std::vector<double> c_fixed;
         if (std::isfinite(o.mu)) {
@@ -1708,6 +1903,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
             rq.PK = PK;
             rq.n_pl = n_pl;
             rq.dtype = dtype;
+            rq.opmode = operand_mode(o.precision);
             rq.nq = 1;
             rq.coef = c.data();
             rq.acc[0] = accK.as<double>();
@@ -1835,7 +2031,8 @@ static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_
         rq.Mt = Ht.as<double>();
         rq.PK = PK;
         rq.n_pl = n_pl;
-        rq.dtype = o.precision;
+        rq.dtype = storage_dtype(o.precision);
+        rq.opmode = operand_mode(o.precision);
         rq.moments = &mom;
         run_chain(ctx, rq);
         kernel_ms += rq.kernel_ms;
@@ -1902,7 +2099,8 @@ static void chebyshev(chess_ctx *ctx, const chess_matrix *M, double lo, double h
     rq.n_pl = n_pl;
     rq.nq = nq;
     rq.coef = coef;
-    rq.dtype = o.precision;
+    rq.dtype = storage_dtype(o.precision);
+    rq.opmode = operand_mode(o.precision);
     for (int q = 0; q < nq; ++q) {
         accs.push_back(std::make_unique<DevBuf>(sizeof(double) * (size_t)PK->nnzb * b * b));
         rq.acc[q] = accs.back()->as<double>();
@@ -1968,7 +2166,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
                           const chess_opts &o, bool use_graph, double *ms_chains) {
     hipStream_t st = ctx->stream;
     const int nsys = (int)idx.size();
-    const int dtype = o.precision;
+    const int dtype = storage_dtype(o.precision);
     std::vector<const Pattern *> PHs, PSs, PKs;
     for (int i : idx) {
         const chess_batch_item &it = items[i];
@@ -2062,6 +2260,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
     sc.n_pl = npls_max;
     sc.nq = 2;
     sc.dtype = dtype;
+    sc.opmode = operand_mode(o.precision);
     sc.coef_tab = stab.data();
     sc.acc[0] = F.accX.as<double>();
     sc.acc[1] = accSinv.as<double>();
@@ -2153,6 +2352,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
     hc.n_pl = npl_max;
     hc.nq = 3;
     hc.dtype = dtype;
+    hc.opmode = operand_mode(o.precision);
     hc.coef_tab = htab.data();
     for (int q = 0; q < 3; ++q) hc.acc[q] = accK[q].as<double>();
     hc.row0 = &row0;

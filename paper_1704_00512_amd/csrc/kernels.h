@@ -64,7 +64,17 @@ struct ProductOperands {
     const void *bt_val;
     const int64_t *c_rp;
     void *c_out;
+    // bfloat16 operand forms of Bt (output-stationary kernel, kStatBF16 and
+    // kStatBF16X3): hi = bf16(x), lo = bf16(x - hi), same block layout
+    const void *bt_hi = nullptr;
+    const void *bt_lo = nullptr;
+    // operand mode of the product: 0 = the storage precision (dtype);
+    // kStatBF16 or kStatBF16X3 (float32 storage, output-stationary kernel only)
+    int opmode = 0;
 };
+
+// Operand modes of the output-stationary product (kernels_stat.hip)
+enum { kStatF32 = 0, kStatBF16 = 1, kStatBF16X3 = 2, kStatF64 = 3 };
 
 // Plan of a product with precomputed hit lists (kernels_listed.hip).  Per
 // tile the output columns j; per column a record of 8 int32:
@@ -121,15 +131,42 @@ struct ListedPlanDev {
     // element offsets of the output pattern (in float64) and byte offsets of
     // the hit lists fit in 31 bits (buffer-descriptor addressing)
     bool off31 = false;
+    // Output-stationary plan (b = 4; null otherwise): the output blocks of
+    // tile t, sorted by hit count, form the groups [st_goff[t], st_goff[t+1])
+    // of st_g slots.  Per group st_ginfo {list offset in 16-byte units,
+    // R | diagonal-slot mask << 16} with R (rounds) a multiple of 8; per group
+    // and slot st_slot {output block (0xFFFFFFFF: none), Bt row start block |
+    // A row start block in the LDS tile << 22}; per slot a list of R two-byte
+    // entries (position in A row | position in Bt row << 8), padded with the
+    // row's zero block (position = row length).  In LDS each tile row is
+    // followed by one zero block (st_ablocks: the largest tile so laid out).
+    const int32_t *st_goff = nullptr;
+    const int32_t *st_ginfo = nullptr;
+    const uint32_t *st_slot = nullptr;
+    const void *st_list = nullptr;
+    int st_g = 0;
+    int st_ablocks = 0;
 };
+
+// The output-stationary product (kernels_stat.hip): mode kStat*, nw waves
+// per workgroup (4, 8 or 16).  lds_out (if not null) receives the LDS bytes
+// and nothing is launched.
+hipError_t launch_stat_product(int mode, int nw, const ListedPlanDev &plan, const ProductOperands &ops,
+                               const Epilogue &ep, hipStream_t st, size_t *lds_out);
+// hi[i] = bf16(in[i]), lo[i] = bf16(in[i] - hi[i]) (lo may be null)
+hipError_t launch_split_bf16(int64_t n, const float *in, unsigned short *hi, unsigned short *lo, hipStream_t st);
 
 hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
                                  const ProductOperands &ops, const Epilogue &ep, hipStream_t st);
-size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan);
+size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan, int opmode = 0);
 // number of kernel variant ids for this dtype / b / plan.cmax (>= 1), and
 // whether id v exists
 int listed_product_variants(int dtype, int b, const ListedPlanDev &plan);
-bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int v);
+bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int v, int opmode = 0);
+// variant ids of the output-stationary kernel: float32 storage 24, 25, 26
+// (8, 4, 16 waves; also the ids for the bfloat16 operand modes), float64
+// storage 10, 11, 12 (4, 8, 16 waves)
+constexpr int kStatVariantF32 = 24, kStatVariantF64 = 10;
 
 // Learned predictor (learned.hip): perceptron sizes, feature histograms.
 constexpr int kMlpIn = 64, kMlpHidden = 128, kMlpOut = 3;

@@ -1456,7 +1456,9 @@ struct LVariant {
     // 1: float32 4x4x1 MFMA, 2: float64 4x4x4 MFMA, 0: vector ALU dot products
     static constexpr int MODE = (B == 4 && CMAX == 4) ? (std::is_same<T, float>::value ? 1 : 2) : 0;
     static constexpr int NW = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 24 : 10);
+    // the last three ids of each MFMA mode are the output-stationary kernel
+    // (kernels_stat.hip) on the plan's groups
+    static constexpr int COUNT = MODE == 0 ? 1 : (MODE == 1 ? 27 : 13);
     // variants 4, 5 (pipelined hit groups), 10-15 (6- and 8-hit groups) and
     // 16-23 (free slot assignment) are float32 only
     static bool ok(int v) { return v >= 0 && v < COUNT && (MODE == 1 || (v != 4 && v != 5)); }
@@ -1528,6 +1530,16 @@ hipError_t launch_l(const ListedPlanDev &plan, const ProductOperands &ops, const
         }
         return hipErrorInvalidValue;
     } else {
+        {
+            // the last three ids: the output-stationary kernel on the plan's groups
+            const int v0 = MODE == 1 ? kStatVariantF32 : kStatVariantF64;
+            const int d = plan.variant - v0;
+            if (d >= 0) {
+                if (d > 2) return hipErrorInvalidValue;
+                const int nw = MODE == 1 ? (d == 0 ? 8 : d == 1 ? 4 : 16) : (d == 0 ? 4 : d == 1 ? 8 : 16);
+                return launch_stat_product(MODE == 1 ? kStatF32 : kStatF64, nw, plan, ops, ep, st, lds_out);
+            }
+        }
         switch (plan.variant) {
             case 0: return launch_v<T, B, CMAX, NW, MODE, EW, false>(plan, ops, ep, st, lds_out);
             case 1: return launch_v<T, B, CMAX, NW, MODE, EW, true>(plan, ops, ep, st, lds_out);
@@ -1611,6 +1623,12 @@ hipError_t launch_lb(const ListedPlanDev &plan, const ProductOperands &ops, cons
 
 hipError_t dispatch_listed(int dtype, int b, const ListedPlanDev &plan, const ProductOperands &ops,
                            const Epilogue &ep, hipStream_t st, size_t *lds_out) {
+    if (ops.opmode != 0) {
+        // bfloat16 operands: the output-stationary kernel on float32 storage
+        const int d = plan.variant - kStatVariantF32;
+        if (dtype != 1 || b != 4 || d < 0 || d > 2) return hipErrorInvalidValue;
+        return launch_stat_product(ops.opmode, d == 0 ? 8 : d == 1 ? 4 : 16, plan, ops, ep, st, lds_out);
+    }
     if (dtype == 0 && b == 4) return launch_lb<double, 4>(plan, ops, ep, st, lds_out);
     if (dtype == 0 && b == 9) return launch_lb<double, 9>(plan, ops, ep, st, lds_out);
     if (dtype == 1 && b == 4) return launch_lb<float, 4>(plan, ops, ep, st, lds_out);
@@ -1631,17 +1649,23 @@ int listed_product_variants(int dtype, int b, const ListedPlanDev &plan) {
     return dtype == 0 ? LVariant<double, 4, 4>::COUNT : LVariant<float, 4, 4>::COUNT;
 }
 
-bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int v) {
+bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int v, int opmode) {
+    const bool stat_ok = b == 4 && plan.st_goff && plan.st_g == (dtype == 0 ? 4 : 16);
+    if (opmode != 0) return dtype == 1 && stat_ok && v >= kStatVariantF32 && v <= kStatVariantF32 + 2;
     if (b == 9 && dtype == 1 && plan.cmax == 2)
         return v >= 0 && v < 5 && (v < 3 || (plan.off31 && plan.entry_width == 1));
     if (b != 4 || plan.cmax != 4) return v == 0;
+    const int v0 = dtype == 0 ? kStatVariantF64 : kStatVariantF32;
+    if (v >= v0) return v <= v0 + 2 && stat_ok;
     if (v >= 16 && !(dtype == 1 && plan.lean_rec && plan.entry_width == 1)) return false;
     return dtype == 0 ? LVariant<double, 4, 4>::ok(v) : LVariant<float, 4, 4>::ok(v);
 }
 
-size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan) {
+size_t listed_product_lds_bytes(int dtype, int b, const ListedPlanDev &plan, int opmode) {
     size_t lds = 0;
-    if (dispatch_listed(dtype, b, plan, ProductOperands{}, Epilogue{}, nullptr, &lds) != hipSuccess)
+    ProductOperands ops{};
+    ops.opmode = opmode;
+    if (dispatch_listed(dtype, b, plan, ops, Epilogue{}, nullptr, &lds) != hipSuccess)
         return (size_t)-1;
     return lds;
 }

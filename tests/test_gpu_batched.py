@@ -127,7 +127,8 @@ def test_batched_rejected_bounds_fall_back_to_gershgorin(gpu_ctx):
         assert np.max(np.abs(r["K"][1].cpu().numpy() - Ko)) < 1e-10
 
 
-@pytest.mark.parametrize("variant,which", [(20, (0, 2, 4)), (21, (0, 2, 4)), (3, (1, 3))])
+@pytest.mark.parametrize("variant,which", [(20, (0, 2, 4)), (21, (0, 2, 4)), (24, (0, 2, 4)),
+                                           (3, (1, 3))])
 def test_batched_forced_kernel_variants(gpu_ctx, monkeypatch, variant, which):
     # the free-slot b = 4 kernels (20, 21) and the pipelined 9 x 9 one (3; with
     # three sums it runs k_listed9) on block-diagonal batches: tiles never

@@ -97,7 +97,8 @@ def chain_check(ctx, ph, H, pk, precision, nq, n_pl=40):
 # (case, precision, forced variant or None for the library's own choice)
 CHAIN_CASES = [(c, p, None) for c in EDGE for p in ("f64", "f32")]
 CHAIN_CASES += [(c, "f32", v) for c in ("diag4", "diag4_wide", "one4", "two4")
-                for v in (0, 8, 12, 16, 20, 21)]
+                for v in (0, 8, 12, 16, 20, 21, 24, 25)]
+CHAIN_CASES += [(c, "f64", v) for c in ("diag4", "diag4_wide", "one4", "two4") for v in (10, 12)]
 CHAIN_CASES += [(c, "f32", v) for c in ("diag9_wide", "one9", "three9") for v in (0, 2, 3)]
 
 
