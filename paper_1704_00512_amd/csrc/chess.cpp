@@ -402,8 +402,8 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
 }
 
 // Output-stationary groups of a listed plan (kernels_stat.hip; b = 4): per
-// tile, the output blocks sorted by hit count (descending; ties in row-major
-// order) and cut into groups of G = 16 (float32 storage) or 4 (float64); a
+// tile, the output blocks in column order (columns by their largest hit count,
+// descending) cut into groups of G = 16 (float32 storage) or 4 (float64); a
 // group runs R rounds, its largest hit count rounded up to 8; each slot's
 // list holds its hits (position in A row i, position in Bt row j) in the
 // order of l, then the row's zero block.  Leaves the plan without groups when
@@ -466,11 +466,38 @@ static void build_stat_groups(chess_ctx *ctx, ListedPlan *P) {
                     o.push_back({(uint32_t)q, r, first, (int)((int64_t)ent.size() - first), j});
                 }
             }
-            std::stable_sort(o.begin(), o.end(), [](const Out &x, const Out &y) { return x.n > y.n; });
+            // column order: the outputs of one column j read the same row j of
+            // Bt, so a group that holds few columns finds their blocks in L1;
+            // columns sorted by their largest hit count keep the counts inside
+            // a group close (little padding)
+            std::vector<int32_t> jj;
+            for (const Out &x : o) jj.push_back(x.j);
+            std::sort(jj.begin(), jj.end());
+            jj.erase(std::unique(jj.begin(), jj.end()), jj.end());
+            std::vector<int> cmax(jj.size(), 0);
+            for (const Out &x : o) {
+                const size_t k = (size_t)(std::lower_bound(jj.begin(), jj.end(), x.j) - jj.begin());
+                cmax[k] = std::max(cmax[k], x.n);
+            }
+            auto colkey = [&](const Out &x) {
+                return cmax[(size_t)(std::lower_bound(jj.begin(), jj.end(), x.j) - jj.begin())];
+            };
+            std::stable_sort(o.begin(), o.end(), [&](const Out &x, const Out &y) {
+                const int kx = colkey(x), ky = colkey(y);
+                if (kx != ky) return kx > ky;
+                if (x.j != y.j) return x.j < y.j;
+                return x.row < y.row;
+            });
+            // outputs with no hit add nothing (their blocks are written as 0 by
+            // a group of their own at the end)
+            std::stable_partition(o.begin(), o.end(), [](const Out &x) { return x.n > 0; });
             int64_t list_units = 0;
             for (size_t g0 = 0; g0 < o.size(); g0 += G) {
                 const size_t g1 = std::min(o.size(), g0 + (size_t)G);
-                const int R = std::max(8, (o[g0].n + 7) & ~7);
+                // rounds: the group's largest hit count, rounded up to 8
+                int nmax = 0;
+                for (size_t k = g0; k < g1; ++k) nmax = std::max(nmax, o[k].n);
+                const int R = std::max(8, (nmax + 7) & ~7);
                 if (R > 0xFFFF) to.overflow = true;
                 uint32_t dmask = 0;
                 for (size_t k = g0; k < g1; ++k)
@@ -1001,11 +1028,10 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
         lp->dev.variant = lp->tuned_variant[opmode];
         return;
     }
-    // untimed default: b = 4 float32, the slots shared among the tile rows
-    // with the prefetch after the last group's loads (or, without that plan,
-    // operands from global memory behind a scheduling barrier); b = 4 float64,
-    // operands from global memory with 8 waves; b = 9 float32, the MFMA kernel
-    // with pipelined columns and 8 waves (or without); variant 0 otherwise
+    // untimed default: b = 4, the output-stationary kernel (float32 with 8
+    // waves, float64 with 16; without its groups, the free-slot kernel or
+    // operands from global memory); b = 9 float32, the MFMA kernel with
+    // pipelined columns and 8 waves (or without); variant 0 otherwise
     auto fits = [&](int v) {
         ListedPlanDev d = lp->dev;
         d.variant = v;
@@ -1018,11 +1044,11 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
     } else if (nvar == 1)
         lp->dev.variant = 0;
     else if (b == 4 && dtype == 1)
-        lp->dev.variant = fits(20) ? 20 : 8;
+        lp->dev.variant = fits(kStatVariantF32) ? kStatVariantF32 : fits(20) ? 20 : 8;
     else if (b == 9)
         lp->dev.variant = fits(3) ? 3 : 2;
     else
-        lp->dev.variant = 2;
+        lp->dev.variant = fits(kStatVariantF64 + 2) ? kStatVariantF64 + 2 : 2;
     if (nvar == 1 || n_pl < 64) return;  // too short a chain to time variants on
     hipStream_t st = ctx->stream;
     DevBuf out(vbytes(lp->c, dtype));
