@@ -299,6 +299,23 @@ int chess_mlp_grad(chess_ctx *ctx, const float *params, const float *x, const fl
  */
 int chess_mlp_adam(chess_ctx *ctx, float *params, const float *grad, float *m, float *v, int64_t n,
                    float lr, float beta1, float beta2, float eps, int32_t step);
+/*
+ * chess_mlp_grad without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid hipMalloc): the same kernels and result as
+ * chess_mlp_grad, with the workspace (and the loss on the device) taken from
+ * a fixed array inside the library instead of `work` and the context.
+ * batch must be 1..CHESS_NOALLOC_MAX_BATCH (else CHESS_E_ARG); the array
+ * holds 256 + CHESS_NOALLOC_MAX_BATCH * 131 * 4 bytes per GPU for the life of
+ * the process.  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (from several contexts or threads) race.  loss (host, may be
+ * NULL): when given, the call waits for it; with NULL it only enqueues
+ * kernels on the context's stream.
+ */
+#define CHESS_NOALLOC_MAX_BATCH 4096
+int chess_mlp_grad_noalloc(chess_ctx *ctx, const float *params, const float *x, const float *hidden,
+                           const float *y, const float *target, int32_t batch, float *grad,
+                           double *loss);
 /* Loads a model blob (host, n = CHESS_MODEL_FLOATS) into the context for
  * CHESS_BOUNDS_LEARNED; CHESS_E_ARG for a wrong size, non-finite entries or a
  * non-positive inverse scale.  chess_model_save copies the loaded blob back. */

@@ -87,12 +87,13 @@ EXPORTS = ["chess_default_opts", "chess_create", "chess_destroy", "chess_last_er
            "chess_chebyshev", "chess_masked_product", "chess_set_progress",
            "chess_features", "chess_mlp_forward", "chess_mlp_grad", "chess_mlp_adam",
            "chess_model_load", "chess_model_save", "chess_fermi_operator_batched",
-           "chess_ssf_to_bcsr", "chess_bcsr_to_ssf", "chess_degree"]
+           "chess_ssf_to_bcsr", "chess_bcsr_to_ssf", "chess_degree", "chess_mlp_grad_noalloc"]
 
 N_FEATURES, MLP_HIDDEN, MLP_OUT = 64, 128, 3
 MLP_PARAMS = MLP_HIDDEN * N_FEATURES + MLP_HIDDEN + MLP_OUT * MLP_HIDDEN + MLP_OUT
 MLP_NORM = 2 * N_FEATURES + 2 * MLP_OUT
 MODEL_FLOATS = MLP_NORM + 3 + MLP_PARAMS
+NOALLOC_MAX_BATCH = 4096
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64,
                                ctypes.c_int64)
@@ -138,6 +139,8 @@ def load():
     L.chess_mlp_forward.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp, vp]
     L.chess_mlp_grad.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp, vp,
                                  P(ctypes.c_double)]
+    L.chess_mlp_grad_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp,
+                                         P(ctypes.c_double)]
     L.chess_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32]
     L.chess_fermi_operator_batched.argtypes = [vp, ctypes.c_int32, P(chess_batch_item),

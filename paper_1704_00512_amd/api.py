@@ -275,6 +275,21 @@ def chess_mlp_grad(ctx: Context, params, x, hidden, y, target, work=None, grad=N
     return grad, (loss.value if want_loss else None)
 
 
+def chess_mlp_grad_noalloc(ctx: Context, params, x, hidden, y, target, grad=None,
+                           want_loss: bool = True):
+    """As chess_mlp_grad with the library's fixed workspace (no device
+    allocation inside the call; pass `grad` to allocate nothing here either).
+    (grad, loss or None)."""
+    B = x.shape[0]
+    if grad is None:
+        grad = torch.empty(_lib.MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = ctypes.c_double(float("nan"))
+    ctx._check(ctx._L.chess_mlp_grad_noalloc(ctx._h, _fptr(params), _fptr(x), _fptr(hidden), _fptr(y),
+                                             _fptr(target), int(B), _fptr(grad),
+                                             ctypes.byref(loss) if want_loss else None))
+    return grad, (loss.value if want_loss else None)
+
+
 def chess_mlp_adam(ctx: Context, params, grad, m, v, step: int, lr: float, beta1=0.9,
                    beta2=0.999, eps=1e-8):
     ctx._check(ctx._L.chess_mlp_adam(ctx._h, _fptr(params), _fptr(grad), _fptr(m), _fptr(v),

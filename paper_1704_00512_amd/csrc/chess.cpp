@@ -2605,6 +2605,10 @@ static int guarded(chess_ctx *ctx, F &&f) {
     }
 }
 
+int ctx_device(const chess_ctx *ctx) { return ctx->device; }
+hipStream_t ctx_stream(const chess_ctx *ctx) { return ctx->stream; }
+void ctx_set_error(chess_ctx *ctx, const char *msg) { ctx->err = msg; }
+
 }  // namespace chess
 
 using chess::Error;
@@ -2671,6 +2675,8 @@ int chess_create(chess_ctx **out, int device, void *stream) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CHESS_E_HIP;
     if (hipSetDevice(device) != hipSuccess) return CHESS_E_HIP;
+    // the fixed workspace of chess_mlp_grad_noalloc: its address on this device
+    if (chess::noalloc_scratch_init(device) != hipSuccess) return CHESS_E_HIP;
     chess_ctx *c = new (std::nothrow) chess_ctx();
     if (!c) return CHESS_E_OOM;
     c->device = device;

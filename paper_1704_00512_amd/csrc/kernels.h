@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+typedef struct chess_ctx chess_ctx;
+
 namespace chess {
 
 // Symbolic plan of one masked block product C = P_C o (A Bt^T), all three in
@@ -167,6 +169,14 @@ bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int 
 // (8, 4, 16 waves; also the ids for the bfloat16 operand modes), float64
 // storage 10, 11, 12 (4, 8, 16 waves)
 constexpr int kStatVariantF32 = 24, kStatVariantF64 = 10;
+
+// Context accessors for entry points outside chess.cpp (chess_ctx is opaque
+// there), and the per-device workspace address of chess_mlp_grad_noalloc
+// (learned.hip), taken once per device when a context is created.
+int ctx_device(const chess_ctx *ctx);
+hipStream_t ctx_stream(const chess_ctx *ctx);
+void ctx_set_error(chess_ctx *ctx, const char *msg);
+hipError_t noalloc_scratch_init(int device);
 
 // Learned predictor (learned.hip): perceptron sizes, feature histograms.
 constexpr int kMlpIn = 64, kMlpHidden = 128, kMlpOut = 3;

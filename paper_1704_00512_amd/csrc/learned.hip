@@ -11,6 +11,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
+#include "../../include/chess.h"
 #include "kernels.h"
 
 namespace chess {
@@ -248,3 +251,82 @@ hipError_t launch_row_features(int b, int nb, const int64_t *rp, const int32_t *
 }
 
 }  // namespace chess
+
+// ---------------------------------------------------------------------------
+// Allocation-free gradient (chess_mlp_grad_noalloc): its workspace is this
+// fixed array - one float64 loss at offset 0, then dy [batch][3] and
+// dh [batch][128] floats from offset 256 - for batches of at most
+// CHESS_NOALLOC_MAX_BATCH rows.  Every GPU that runs the library holds its
+// own copy until the process ends; in host code `scratch` names a host-side
+// stand-in, so its device address is taken once per device (with that device
+// current) by noalloc_scratch_init and used everywhere instead of the name.
+// The kernels write every workspace value before reading it, so nothing needs
+// clearing between calls; calls that overlap on one GPU share it and race.
+// ---------------------------------------------------------------------------
+namespace chess {
+namespace {
+constexpr size_t kNoAllocBytes =
+    256 + (size_t)CHESS_NOALLOC_MAX_BATCH * (kMlpOut + kMlpHidden) * sizeof(float);
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+}  // namespace chess
+
+static __device__ __align__(256) unsigned char scratch[chess::kNoAllocBytes];
+
+namespace chess {
+
+hipError_t noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
+}  // namespace chess
+
+extern "C" int chess_mlp_grad_noalloc(chess_ctx *ctx, const float *params, const float *x,
+                                      const float *hidden, const float *y, const float *target,
+                                      int32_t batch, float *grad, double *loss) {
+    using namespace chess;
+    if (!ctx) return CHESS_E_ARG;
+    if (!params || !x || !hidden || !y || !target || !grad || batch <= 0) {
+        ctx_set_error(ctx, "mlp_grad_noalloc: null pointer or empty batch");
+        return CHESS_E_ARG;
+    }
+    if (batch > CHESS_NOALLOC_MAX_BATCH) {
+        ctx_set_error(ctx, "mlp_grad_noalloc: batch exceeds CHESS_NOALLOC_MAX_BATCH (the fixed workspace)");
+        return CHESS_E_ARG;
+    }
+    const int dev = ctx_device(ctx);
+    hipStream_t st = ctx_stream(ctx);
+    hipError_t e = hipSetDevice(dev);
+    void *base = nullptr;
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+    }
+    if (e != hipSuccess || !base) {
+        ctx_set_error(ctx, "mlp_grad_noalloc: no workspace address for this device");
+        return CHESS_E_HIP;
+    }
+    double *dl = static_cast<double *>(base);
+    float *dy = reinterpret_cast<float *>(static_cast<unsigned char *>(base) + 256);
+    float *dh = dy + (size_t)batch * kMlpOut;
+    e = launch_mlp_grad(params, x, hidden, y, target, batch, dy, dh, grad, loss ? dl : nullptr, st);
+    if (e == hipSuccess && loss) {
+        e = hipMemcpyAsync(loss, dl, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e != hipSuccess) {
+        ctx_set_error(ctx, hipGetErrorString(e));
+        return CHESS_E_HIP;
+    }
+    ctx_set_error(ctx, "no error");
+    return CHESS_OK;
+}
