@@ -10,15 +10,23 @@ Printed JSON line:
   value        Chebyshev SpMM throughput in algorithmic GB/s: algorithmic
                bytes of every chain-product launch in the timed steps divided
                by their device time (HIP events on the library's stream);
-  ms_per_step  density-kernel time to solution of the fast form (float32
-               chain, Lanczos bounds checked by Eq. 6);
-  roofline     the chain product kernel against MI355X peaks;
+  ms_per_step  density-kernel time to solution of the timed form (float32
+               chain, bounds from the learned predictor - or Lanczos with
+               --form lanczos - checked by Eq. 6, tol_fit 1e-6);
+  roofline     the chain product kernel against MI355X peaks, the call as a
+               whole and each pass (moments only / accumulating) on its own;
+  reference_f64  K from the float64 chain with Lanczos bounds and tol_fit
+               1e-10; every form's K is compared with it (max_abs_err_vs_ref);
+  form_*_f32   the other float32 form (Lanczos or learned), untimed;
+  eigs_window  eigenvalues in [mu - 0.05, mu + 0.05] Ha from one float32
+               chain's moments;
   cpu_baseline the oracle's chain (plain C, float64) on a bounded sample of
-               the same workload;
+               the same workload, and its estimated time for the call's chain;
   plain_f64    time to solution of the plain float64 form (Gershgorin bounds,
-               moments pass + bisection + accumulating pass) and the max-abs
-               difference of the two kernels; with an estimate (not run) of
-               the paper-literal form, which forms K at every bisection step.
+               moments pass + bisection + accumulating pass, same tol_fit),
+               its kernel's roofline fraction, its error against the
+               reference, and an estimate (not run) of the paper-literal
+               form, which forms K at every bisection step.
 """
 from __future__ import annotations
 
@@ -71,7 +79,7 @@ def count_triples(sysm):
 
 def kernel_source_hash():
     h = hashlib.sha1()
-    for f in ("kernels.hip", "kernels_listed.hip", "kernels.h"):
+    for f in ("kernels.hip", "kernels_listed.hip", "kernels_stat.hip", "kernels.h"):
         h.update(open(os.path.join(ROOT, "paper_1704_00512_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:12]
 
@@ -231,7 +239,12 @@ def main():
     ap.add_argument("--chain-only", type=int, default=0, metavar="N_PL",
                     help="only run one N_PL-term chain (one accumulator) on the workload's H, "
                          "for counter collection")
-    ap.add_argument("--precision", default="f32", help="--chain-only: f32 or f64")
+    ap.add_argument("--precision", default="f32", help="--chain-only: f32, f64, bf16 or bf16x3")
+    ap.add_argument("--form", default="learned", choices=("learned", "lanczos", "gershgorin"),
+                    help="bounds of the timed float32 form (learned: the loaded predictor)")
+    ap.add_argument("--no-ref", action="store_true", help="skip the float64 reference K")
+    ap.add_argument("--no-other", action="store_true", help="skip the other float32 form")
+    ap.add_argument("--no-eigs", action="store_true", help="skip the eigenvalue window")
     ap.add_argument("--variant", type=int, default=-1,
                     help="--chain-only: force this chain-kernel variant (CHESS_LISTED_VARIANT)")
     args = ap.parse_args()
@@ -278,7 +291,8 @@ def main():
             log(f"copy {i}: {n * 4} bytes")
         return
 
-    from paper_1704_00512_amd import BlockPattern, Context, chess_fermi_operator, chess_matrix_power
+    from paper_1704_00512_amd import (BlockPattern, Context, chess_eigs_in_interval,
+                                      chess_fermi_operator, chess_matrix_power, chess_model_load)
     from workloads.generator import CONFIGS, make_config
 
     log(f"generating workload {args.workload} {CONFIGS[args.workload]}")
@@ -293,8 +307,17 @@ def main():
     pk = BlockPattern.from_host(sysm.b, sysm.pat_k.row_ptr, sysm.pat_k.col_idx, dev)
     K = pk.zeros()
     ctx = Context(0)
-    fast = dict(precision="f32", bounds_mode="lanczos", store_history=1, tol_fit=1e-6,
-                tol_fit_s=1e-7)
+    model_path = os.path.join(ROOT, "paper_1704_00512_amd", "predictor_model.npy")
+    have_model = os.path.exists(model_path)
+    if have_model:
+        chess_model_load(ctx, np.load(model_path))
+    form = args.form
+    if form == "learned" and not have_model:
+        log("no predictor model: the timed form falls back to Lanczos bounds")
+        form = "lanczos"
+    tol_fit, tol_fit_s = 1e-6, 1e-7
+    fast = dict(precision="f32", bounds_mode=form, store_history=1, tol_fit=tol_fit,
+                tol_fit_s=tol_fit_s)
 
     def run(opts):
         return chess_fermi_operator(ctx, H, ph, S, ph, pk, sysm.n_electrons, sysm.kT, out=K, **opts)
@@ -311,7 +334,7 @@ def main():
         infos.append(info)
         log(f"step {i}: {info['ms_total']:.1f} ms mu={info['mu']:.6f} n_pl={info['n_pl']} "
             f"passes={info['passes']} bounds=[{info['lo']:.4f},{info['hi']:.4f}] "
-            f"trKS={info['tr_ks']:.6f} penalty={info['penalty']:.2e}")
+            f"trKS={info['tr_ks']:.6f} penalty={info['penalty']:.2e} fallback={info['fallback']}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall / args.steps * 1e3
@@ -334,24 +357,48 @@ def main():
     tflops = flops_launch * launches_call / (kern_ms * 1e-3) / 1e12
     t_hbm = bytes_call / (HBM_PEAK_GBS * 1e9)
     t_alu = flops_launch * launches_call / (FP32_PEAK_TFLOPS * 1e12)
-    bound = "hbm" if t_hbm >= t_alu else "mfma"
     avg_launch_ms = kern_ms / max(launches_call, 1)
     traffic = measured_traffic(args.workload)
-    if bound == "hbm":
+    # each pass against its own roof: the moments pass (no float64 sum) and
+    # the accumulating pass, from the library's per-pass device times
+    per_pass = []
+    acc_ms = sum(i.get("ms_chain_kernel_acc", float("nan")) for i in infos) / len(infos)
+    if not hist and acc_ms == acc_ms and steps_per_pass > 0:
+        for name, byts, ms in (("moments", b1, kern_ms - acc_ms), ("accumulate", b2, acc_ms)):
+            ms_l = ms / steps_per_pass
+            th, ta = byts / (HBM_PEAK_GBS * 1e9), flops_launch / (FP32_PEAK_TFLOPS * 1e12)
+            if th >= ta:
+                ach = byts / (ms_l * 1e-3) / 1e9
+                per_pass.append(dict(pass_=name, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS,
+                                     unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), avg_launch_ms=round(ms_l, 4),
+                                     algorithmic_bytes=int(byts)))
+            else:
+                ach = flops_launch / (ms_l * 1e-3) / 1e12
+                per_pass.append(dict(pass_=name, bound="mfma", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS,
+                                     unit="TFLOP/s", frac=round(ach / FP32_PEAK_TFLOPS, 4),
+                                     avg_launch_ms=round(ms_l, 4), flops=flops_launch))
+    # the call as a whole: HBM when its bytes take longer than its flops
+    if t_hbm >= t_alu:
         roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(gbs / HBM_PEAK_GBS, 4))
     else:
         roof = dict(bound="mfma", achieved=round(tflops, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(tflops / FP32_PEAK_TFLOPS, 4))
-    kname = ("k_lean<...> (chain product, MFMA slots shared among tile rows)"
-             if 16 <= info["kernel_variant"] <= 23 else "k_listed<float,4,4,...> (chain product)")
-    roof.update(traffic=traffic, kernel=f"{kname}, variant {info['kernel_variant']} chosen by timing",
+    v = info["kernel_variant"]
+    kname = ("k_stat<float32> (output-stationary chain product)" if 24 <= v <= 26 else
+             "k_lean<...> (chain product, MFMA slots shared among tile rows)" if 16 <= v <= 23 else
+             "k_listed<float,4,4,...> (chain product)")
+    roof.update(traffic=traffic, kernel=f"{kname}, variant {v} chosen by timing",
                 avg_launch_ms=round(avg_launch_ms, 4),
                 algorithmic_bytes_per_call=int(bytes_call), launches_per_call=launches_call,
                 flops_per_launch=flops_launch, achieved_gbs=round(gbs, 1),
                 achieved_tflops=round(tflops, 2), t_hbm_ideal_ms=round(t_hbm * 1e3, 2),
-                t_alu_ideal_ms=round(t_alu * 1e3, 2), kernel_source_sha1=kernel_source_hash())
+                t_alu_ideal_ms=round(t_alu * 1e3, 2), passes=[{("pass" if k == "pass_" else k): x
+                                                              for k, x in d.items()} for d in per_pass],
+                kernel_source_sha1=kernel_source_hash())
 
+    form_name = {"lanczos": "Lanczos bounds", "learned": "learned bounds and mu bracket (predictor)",
+                 "gershgorin": "Gershgorin bounds"}[form]
     out = dict(metric=METRIC, value=round(gbs, 1), unit="GB/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_per_step, 2), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
@@ -359,11 +406,73 @@ def main():
                                     f"{sysm.n} rows, P_H {sysm.pat_h.nnzb} blocks, P_K "
                                     f"{sysm.pat_k.nnzb} blocks, kT {sysm.kT} Ha, erfc, "
                                     f"N_e {sysm.n_electrons:g}",
-                           form="float32 chain, Lanczos bounds + Eq. 6 check, tol_fit 1e-6",
+                           form=f"float32 chain, {form_name} checked by Eq. 6, tol_fit {tol_fit:g}",
                            n_pl=n_pl, n_pl_s=info["n_pl_s"], passes=passes,
                            time_to_solution_ms=round(ms_per_step, 2)),
                roofline=roof)
 
+    def run_form(name, opts, progress=False):
+        """One untimed call of another form; (info, wall ms, K on the host)."""
+        log(f"form {name}: {opts}")
+        if progress:
+            ctx.set_progress(lambda stage, done, total: log(f"  {name} {stage}: {done}/{total}"),
+                             every=1024)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, inf = run(opts)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        if progress:
+            ctx.set_progress(None)
+        return inf, ms, K.cpu().numpy()
+
+    K_ref = None
+    if not args.no_ref:
+        # reference: float64 chain, tight (Lanczos) bounds, tol_fit 1e-10; the
+        # float64 path is parity-tested against the oracle to 1e-10
+        rinfo, rms, K_ref = run_form("reference", dict(precision="f64", bounds_mode="lanczos",
+                                                       store_history=0, tol_fit=1e-10,
+                                                       tol_fit_s=1e-12), progress=True)
+        out["reference_f64"] = dict(ms=round(rms, 1), n_pl=rinfo["n_pl"], n_pl_s=rinfo["n_pl_s"],
+                                    bounds=[rinfo["lo"], rinfo["hi"]], mu=rinfo["mu"],
+                                    tol_fit=1e-10, tr_ks=rinfo["tr_ks"])
+        err = float(np.max(np.abs(K_fast - K_ref)))
+        out["config"]["max_abs_err_vs_ref"] = err
+        log(f"reference f64: {rms:.0f} ms n_pl={rinfo['n_pl']}; max|K_fast - K_ref| = {err:.2e}")
+    # the other single-precision form (learned <-> Lanczos), untimed
+    other = "lanczos" if form == "learned" else ("learned" if have_model else None)
+    if other and not args.no_other:
+        oinfo, oms, K_o = run_form(other, dict(fast, bounds_mode=other))
+        rec = dict(ms=round(oms, 1), n_pl=oinfo["n_pl"], passes=oinfo["passes"],
+                   bounds=[oinfo["lo"], oinfo["hi"]], mu=oinfo["mu"],
+                   bisect_iters=oinfo["bisect_iters"], fallback=oinfo["fallback"],
+                   pred=[oinfo["pred_lo"], oinfo["pred_hi"], oinfo["pred_mu"]])
+        if K_ref is not None:
+            rec["max_abs_err_vs_ref"] = float(np.max(np.abs(K_o - K_ref)))
+        out[f"form_{other}_f32"] = rec
+        out["config"]["bisect_iters"] = info["bisect_iters"]
+        if form == "learned":
+            out["config"]["fallback"] = info["fallback"]
+            out["config"]["pred"] = [info["pred_lo"], info["pred_hi"], info["pred_mu"]]
+        log(f"{other}: {oms:.0f} ms n_pl={oinfo['n_pl']} bisect={oinfo['bisect_iters']}")
+    if not args.no_eigs:
+        # eigenvalues in [mu - 0.05, mu + 0.05] Ha (Sec. "Extraction of selected
+        # eigenvalues"): moments of one float32 chain at the default width
+        mu = info["mu"]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ev, einfo = chess_eigs_in_interval(ctx, H, ph, S, ph, mu - 0.05, mu + 0.05, pk,
+                                           capacity=1 << 20, precision="f32", bounds_mode="lanczos",
+                                           tol_fit=1e-6, tol_fit_s=tol_fit_s)
+        torch.cuda.synchronize()
+        ems = (time.perf_counter() - t) * 1e3
+        gaps = np.diff(ev) if ev.size > 1 else np.zeros(0)
+        out["eigs_window"] = dict(lo=mu - 0.05, hi=mu + 0.05, count=int(ev.size), n_pl=einfo["n_pl"],
+                                  width=1e-3, ms=round(ems, 1),
+                                  mean_spacing=float(gaps.mean()) if gaps.size else None,
+                                  spacings_below_width=int(np.sum(gaps < 1e-3)),
+                                  ms_chain_kernel=round(einfo["ms_chain_kernel"], 1))
+        log(f"eigenvalues in [mu-0.05, mu+0.05]: {ev.size} in {ems:.0f} ms, n_pl={einfo['n_pl']}")
     if args.warm_start:
         log("warm start")
         X = pk.zeros()
@@ -429,10 +538,20 @@ def main():
         ctx.set_progress(None)
         K_plain = K.cpu().numpy()
         diff = float(np.max(np.abs(K_plain - K_fast)))
+        pl_steps = max(pinfo["n_pl"] - 2, 0) * pinfo["passes"]
         out["plain_f64"] = dict(ms=round(tp, 1), n_pl=pinfo["n_pl"], passes=pinfo["passes"],
                                 bounds=[pinfo["lo"], pinfo["hi"]], mu=pinfo["mu"],
                                 max_abs_diff_fast_vs_plain=diff,
-                                speedup_fast_vs_plain=round(tp / ms_per_step, 2))
+                                speedup_fast_vs_plain=round(tp / ms_per_step, 2),
+                                avg_launch_ms=round(pinfo["ms_chain_kernel"] / max(pl_steps, 1), 4),
+                                terms_ratio=round(pinfo["n_pl"] * pinfo["passes"] / max(n_pl * passes, 1), 3))
+        # the float64 chain launch against its own roof (the accumulating
+        # pass is HBM-bound, the moments pass float64-MFMA-bound)
+        b64 = chain_step_cost(sysm, 8, 1, False)
+        t64 = max(b64 / (HBM_PEAK_GBS * 1e9), flops_launch / (FP64_PEAK_TFLOPS * 1e12))
+        out["plain_f64"]["frac_of_roofline"] = round(t64 * 1e3 / out["plain_f64"]["avg_launch_ms"], 4)
+        if K_ref is not None:
+            out["plain_f64"]["max_abs_err_vs_ref"] = float(np.max(np.abs(K_plain - K_ref)))
         # the paper-literal form forms K and checks Tr(KS) at every bisection
         # step; with no room for the stored T_k at this size, each step is a
         # whole accumulating pass plus the post-transform (not run: about
@@ -449,7 +568,14 @@ def main():
             f"paper-literal estimate {lit:.0f} ms ({pinfo['bisect_iters']} steps)")
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(sysm)
+        cb = cpu_baseline(sysm)
+        # the oracle's time for the chain steps of the timed call (both passes
+        # and the S chain), from its measured time per step; the sandwich
+        # products and host work of the call are not included
+        nsteps = max(n_pl - 2, 0) * passes + max(info["n_pl_s"] - 2, 0)
+        cb["chain_time_to_solution_estimate_ms"] = round(cb["ms_per_step"] * nsteps, 1)
+        cb["chain_steps_of_the_call"] = nsteps
+        out["cpu_baseline"] = cb
     ctx.close()
     print(json.dumps(out), flush=True)
 

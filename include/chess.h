@@ -185,6 +185,9 @@ typedef struct {
      * In a batch they come from the system's first attempt, or from the
      * Gershgorin redo when its bounds were rejected. */
     double homo, lumo;
+    /* chess_fermi_operator: the part of ms_chain_kernel spent in passes that
+     * accumulate K' (the moments-only passes make up the rest); 0 elsewhere */
+    double ms_chain_kernel_acc;
 } chess_info;
 
 /*

@@ -65,7 +65,8 @@ class chess_info(ctypes.Structure):
                 ("pred_mu", ctypes.c_double), ("ms_learned", ctypes.c_double),
                 ("energy", ctypes.c_double), ("energy_wide", ctypes.c_double),
                 ("kt_used", ctypes.c_double), ("kt_halvings", ctypes.c_int32),
-                ("homo", ctypes.c_double), ("lumo", ctypes.c_double)]
+                ("homo", ctypes.c_double), ("lumo", ctypes.c_double),
+                ("ms_chain_kernel_acc", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

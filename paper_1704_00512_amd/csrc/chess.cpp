@@ -1781,7 +1781,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     std::vector<double> mom;
     int n_pl = 0, reexp = 0, passes = 0;
     double penalty = std::numeric_limits<double>::quiet_NaN();
-    double ms_chain = 0.0, kernel_ms = 0.0;
+    double ms_chain = 0.0, kernel_ms = 0.0, kernel_ms_acc = 0.0;
     int variant = -1;
     bool have_hist = false;
     Timer tm(st);
@@ -1839,6 +1839,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         run_chain(ctx, rq);
         ms_chain += tm.stop();
         kernel_ms += rq.kernel_ms;
+        if (rq.nq > 0) kernel_ms_acc += rq.kernel_ms;
         variant = rq.variant;
         passes++;
         const hostmath::BoundsCheck chk = hostmath::bounds_check(mom, n);
@@ -1935,6 +1936,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
             rq.acc[0] = accK.as<double>();
             run_chain(ctx, rq);
             kernel_ms += rq.kernel_ms;
+            kernel_ms_acc += rq.kernel_ms;
             variant = rq.variant;
             passes++;
         }
@@ -1968,6 +1970,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         info->ms_mu = ms_mu;
         info->ms_post = t_end - t_post0;
         info->ms_chain_kernel = kernel_ms;
+        info->ms_chain_kernel_acc = kernel_ms_acc;
         info->kernel_variant = variant;
         info->pred_lo = pred[0];
         info->pred_hi = pred[1];
