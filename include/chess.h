@@ -86,9 +86,13 @@ enum {
 enum {
     CHESS_BOUNDS_GERSHGORIN = 0, /* Gershgorin discs: rigorous, wide */
     CHESS_BOUNDS_LANCZOS = 1,    /* a few Lanczos steps plus a margin: tight, checked by Eq. 6 */
-    CHESS_BOUNDS_LEARNED = 2     /* the loaded predictor (chess_model_load): bounds and a mu
+    CHESS_BOUNDS_LEARNED = 2,    /* the loaded predictor (chess_model_load): bounds and a mu
                                     bracket from matrix statistics, checked by Eq. 6 and the
                                     growth test; the Gershgorin interval is the fallback */
+    CHESS_BOUNDS_LEARNED_LANCZOS = 3 /* the predictor's interval intersected with the
+                                    CHESS_BOUNDS_LANCZOS one, and its mu bracket; when Eq. 6 or
+                                    the growth test rejects the intersection, the Lanczos
+                                    interval (batched calls: the Gershgorin one) */
 };
 
 typedef struct chess_ctx chess_ctx;
@@ -188,6 +192,9 @@ typedef struct {
     /* chess_fermi_operator: the part of ms_chain_kernel spent in passes that
      * accumulate K' (the moments-only passes make up the rest); 0 elsewhere */
     double ms_chain_kernel_acc;
+    /* chess_fermi_operator: chain kernel variant of the moments-only passes
+     * (kernel_variant is that of the last pass; -1 if there was none) */
+    int32_t kernel_variant_moments;
 } chess_info;
 
 /*

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libchess.so")
 CHESS_OK = 0
 CHESS_F64, CHESS_F32, CHESS_BF16, CHESS_BF16X3 = 0, 1, 2, 3
 CHESS_ERFC, CHESS_FERMI_DIRAC = 0, 1
-CHESS_BOUNDS_GERSHGORIN, CHESS_BOUNDS_LANCZOS = 0, 1
+CHESS_BOUNDS_GERSHGORIN, CHESS_BOUNDS_LANCZOS, CHESS_BOUNDS_LEARNED, CHESS_BOUNDS_LEARNED_LANCZOS = 0, 1, 2, 3
 CHESS_FN_ERFC, CHESS_FN_FERMI_DIRAC, CHESS_FN_POWER = 0, 1, 2
 
 ERRORS = {
@@ -66,7 +66,7 @@ class chess_info(ctypes.Structure):
                 ("energy", ctypes.c_double), ("energy_wide", ctypes.c_double),
                 ("kt_used", ctypes.c_double), ("kt_halvings", ctypes.c_int32),
                 ("homo", ctypes.c_double), ("lumo", ctypes.c_double),
-                ("ms_chain_kernel_acc", ctypes.c_double)]
+                ("ms_chain_kernel_acc", ctypes.c_double), ("kernel_variant_moments", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

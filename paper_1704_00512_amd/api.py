@@ -99,7 +99,7 @@ def default_opts(**kw) -> _lib.chess_opts:
                 raise ValueError(f"{k} must be a contiguous float64 CUDA tensor")
             setattr(o, k, None if v is None else v.data_ptr())
         elif k == "bounds_mode" and isinstance(v, str):
-            o.bounds_mode = {"gershgorin": 0, "lanczos": 1, "learned": 2}[v]
+            o.bounds_mode = {"gershgorin": 0, "lanczos": 1, "learned": 2, "learned_lanczos": 3}[v]
         else:
             setattr(o, k, v)
     return o

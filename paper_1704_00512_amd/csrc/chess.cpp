@@ -132,6 +132,8 @@ struct EmbedMap {
 struct ProductPlan {
     const Pattern *a = nullptr, *bt = nullptr, *c = nullptr;
     int dtype = 0;
+    std::vector<int32_t> breaks;     // rows where a tile must start (batches: system starts)
+    std::vector<int32_t> tile_row0;  // host copy, ntiles + 1
     ProductPlanDev dev;
     DevBuf d_tile_row0, d_u_off, d_u_cols, d_u_pos, d_j_off, d_j_cols, d_j_pos, d_j_rec;
 };
@@ -141,7 +143,9 @@ struct ListedPlan {
     const Pattern *a = nullptr, *bt = nullptr, *c = nullptr;
     int dtype = 0;
     bool usable = false;  // false: rows too long for the list format
-    int tuned_variant[3] = {-1, -1, -1};  // fastest kernel variant per operand mode (-1: not timed yet)
+    // fastest kernel variant per operand mode, for passes without and with
+    // float64 sums (-1: not timed yet)
+    int tuned_variant[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
     std::vector<int32_t> breaks;     // rows where a tile must start (batches: system starts)
     std::vector<int32_t> tile_row0;  // host copy, ntiles + 1
     ListedPlanDev dev;
@@ -283,16 +287,21 @@ static int operand_mode(int precision) {
     return precision == CHESS_BF16 ? kStatBF16 : precision == CHESS_BF16X3 ? kStatBF16X3 : 0;
 }
 
-// Symbolic plan of C = P_C o (A Bt^T) (see kernels.h).
+// Symbolic plan of C = P_C o (A Bt^T) (see kernels.h); tiles start at every
+// row in `breaks` (batches: the first row of each system).
 static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Pattern *Bt,
-                                   const Pattern *C, int dtype) {
+                                   const Pattern *C, int dtype, const std::vector<int32_t> &breaks = {}) {
     for (auto &e : ctx->plans)
-        if (e->a == A && e->bt == Bt && e->c == C && e->dtype == dtype) return e.get();
+        if (e->a == A && e->bt == Bt && e->c == C && e->dtype == dtype && e->breaks == breaks) return e.get();
     auto P = std::make_unique<ProductPlan>();
     P->a = A;
     P->bt = Bt;
     P->c = C;
     P->dtype = dtype;
+    P->breaks = breaks;
+    std::vector<char> is_break(A->nb + 1, 0);
+    for (int32_t r : breaks)
+        if (r >= 0 && r <= A->nb) is_break[r] = 1;
     const int b = A->b;
     const int cmax = pick_cmax(dtype, b);
     const size_t block_bytes = (size_t)b * b * (dtype == 1 ? 4 : 8);
@@ -311,7 +320,7 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
         int64_t blocks = 0;
         while (r < A->nb && r - row0 < cmax) {
             const int64_t len = A->rp[r + 1] - A->rp[r];
-            if (r > row0 && blocks + len > budget_blocks) break;
+            if (r > row0 && (blocks + len > budget_blocks || is_break[r])) break;
             blocks += len;
             ++r;
         }
@@ -377,6 +386,7 @@ static const ProductPlan *get_plan(chess_ctx *ctx, const Pattern *A, const Patte
     upload(P->d_j_pos, j_pos, st);
     upload(P->d_j_rec, j_rec, st);
     HIPCHECK(hipStreamSynchronize(st));
+    P->tile_row0 = tile_row0;
     ProductPlanDev &d = P->dev;
     d.ntiles = (int)tile_row0.size() - 1;
     d.cmax = cmax;
@@ -1009,9 +1019,15 @@ struct ChainRequest {
 // for it times every variant on its own operands (one warm-up and three timed
 // launches each, written to a scratch output) and the fastest one is kept for
 // the plan's lifetime.
+// Chooses the kernel variant of a chain pass by timing them on its first
+// product; passes with float64 sums (nacc > 0, acc = the pass's sums, left
+// unchanged: the timed launches add them with weight 0) are timed apart
+// from passes without.
 static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int n_pl,
                                   const void *a, const void *bt, const void *prev, int opmode = 0,
-                                  const void *bt_hi = nullptr, const void *bt_lo = nullptr) {
+                                  const void *bt_hi = nullptr, const void *bt_lo = nullptr,
+                                  int nacc = 0, double *const *acc = nullptr) {
+    const int pass = nacc > 0 ? 1 : 0;
     const int b = lp->a->b;
     const int nvar = listed_product_variants(dtype, b, lp->dev);
     if (const char *env = std::getenv("CHESS_LISTED_VARIANT")) {
@@ -1024,8 +1040,8 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
             CHESS_THROW(CHESS_E_UNSUPPORTED, "kernel variant %ld needs more than 160 KB of LDS", v);
         return;
     }
-    if (lp->tuned_variant[opmode] >= 0) {
-        lp->dev.variant = lp->tuned_variant[opmode];
+    if (lp->tuned_variant[opmode][pass] >= 0) {
+        lp->dev.variant = lp->tuned_variant[opmode][pass];
         return;
     }
     // untimed default: b = 4, the output-stationary kernel (float32 with 8
@@ -1067,6 +1083,11 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
     ep.alpha = 2.0;
     ep.beta = -1.0;
     ep.prev = prev;
+    ep.nacc = acc ? nacc : 0;
+    for (int q = 0; q < ep.nacc; ++q) {
+        ep.acc[q] = acc[q];
+        ep.coef[q] = 0.0;
+    }
     Timer tm(st);
     double best = 0.0;
     int best_v = -1;
@@ -1084,7 +1105,7 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
         }
     }
     if (best_v < 0) best_v = lp->dev.variant;
-    lp->tuned_variant[opmode] = best_v;
+    lp->tuned_variant[opmode][pass] = best_v;
     lp->dev.variant = best_v;
 }
 
@@ -1120,7 +1141,8 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     if (rq.n_pl > 1)
         HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, emb->d_map_t.as<int64_t>(), rq.Mt, U1.p, 1, st));
     if (lplan->usable) {
-        select_listed_variant(ctx, lplan, dtype, rq.n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p);
+        select_listed_variant(ctx, lplan, dtype, rq.n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p, rq.nq,
+                              rq.acc);
         rq.variant = lplan->dev.variant;
     }
     for (int q = 0; q < rq.nq; ++q) {
@@ -1213,7 +1235,11 @@ static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
     const EmbedMap *emb = get_embed(ctx, PM, PK, "M~ in the chain pattern");
     const std::vector<int32_t> breaks(row0.begin(), row0.end() - 1);
     ListedPlan *lp = get_listed_plan(ctx, PK, PM, PK, dtype, breaks);
-    if (!lp->usable) CHESS_THROW(CHESS_E_UNSUPPORTED, "batched chain: rows too long for the listed product");
+    // rows too long for the hit lists: the searching product, on tiles that
+    // also start at every system
+    const ProductPlan *plan = lp->usable ? nullptr : get_plan(ctx, PK, PM, PK, dtype, breaks);
+    if (!lp->usable && rq.opmode != 0)
+        CHESS_THROW(CHESS_E_UNSUPPORTED, "bfloat16 operands need b = 4 and rows of at most 254 blocks");
     const size_t tb = vbytes(PK, dtype);
     DevBuf U0(tb), U1(tb), Bt(vbytes(PM, dtype) + 16384);
     HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, PM->d_tmap.as<int64_t>(), rq.Mt, Bt.p, 1, st));
@@ -1229,8 +1255,12 @@ static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
         HIPCHECK(launch_split_bf16(nv, Bt.as<float>(), Bhi.as<unsigned short>(),
                                    rq.opmode == kStatBF16X3 ? Blo.as<unsigned short>() : nullptr, st));
     }
-    select_listed_variant(ctx, lp, dtype, n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p);
-    rq.variant = lp->dev.variant;
+    if (lp->usable) {
+        select_listed_variant(ctx, lp, dtype, n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p, rq.nq, rq.acc);
+        rq.variant = lp->dev.variant;
+    } else {
+        rq.variant = -1;
+    }
     DevBuf dcoef(sizeof(double) * (size_t)std::max(rq.nq, 1) * n_pl * nsys);
     if (rq.nq)
         HIPCHECK(hipMemcpyAsync(dcoef.p, rq.coef_tab, sizeof(double) * (size_t)rq.nq * n_pl * nsys, hipMemcpyHostToDevice, st));
@@ -1245,12 +1275,13 @@ static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
                                          rq.acc[q] + off, st));
         }
     }
-    const int ntiles = lp->dev.ntiles;
+    const std::vector<int32_t> &tr0 = lp->usable ? lp->tile_row0 : plan->tile_row0;
+    const int ntiles = (int)tr0.size() - 1;
     std::vector<int32_t> seg(nsys + 1);
     {
         int t = 0;
         for (int sy = 0; sy <= nsys; ++sy) {
-            while (t < ntiles && lp->tile_row0[t] < row0[sy]) ++t;
+            while (t < ntiles && tr0[t] < row0[sy]) ++t;
             seg[sy] = t;
         }
     }
@@ -1281,7 +1312,10 @@ static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
             ep.coef_sys[q] = dcoef.as<double>() + ((size_t)q * n_pl + k + 1) * nsys;
         }
         ep.trace_partial = pd + (size_t)(k + 1) * ntiles;
-        product_listed(ctx, dtype, lp, ucur, Bt.p, uprev, ep, rq.opmode, Bhi.p, Blo.p);
+        if (lp->usable)
+            product_listed(ctx, dtype, lp, ucur, Bt.p, uprev, ep, rq.opmode, Bhi.p, Blo.p);
+        else
+            product(ctx, dtype, plan, ucur, Bt.p, uprev, ep);
         std::swap(ucur, uprev);
     };
     Timer tm(st);
@@ -1342,7 +1376,7 @@ static chess_opts resolve_opts(const chess_opts *o) {
         CHESS_THROW(CHESS_E_UNSUPPORTED, "precision %d", r.precision);
     if (r.smearing != CHESS_ERFC && r.smearing != CHESS_FERMI_DIRAC) CHESS_THROW(CHESS_E_ARG, "smearing %d", r.smearing);
     if (r.bounds_mode != CHESS_BOUNDS_GERSHGORIN && r.bounds_mode != CHESS_BOUNDS_LANCZOS &&
-        r.bounds_mode != CHESS_BOUNDS_LEARNED)
+        r.bounds_mode != CHESS_BOUNDS_LEARNED && r.bounds_mode != CHESS_BOUNDS_LEARNED_LANCZOS)
         CHESS_THROW(CHESS_E_ARG, "bounds_mode %d", r.bounds_mode);
     const double deftol = r.precision == CHESS_F64 ? 1e-10 : r.precision == CHESS_BF16 ? 1e-4 : 1e-6;
     if (!(r.tol_fit > 0)) r.tol_fit = deftol;
@@ -1746,7 +1780,10 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     const bool br_given = std::isfinite(br[0]) && std::isfinite(br[1]);
     Features fe;
     double ms_learned = 0.0;
-    if (!given && o.bounds_mode == CHESS_BOUNDS_LEARNED) {
+    // interval taken when the predicted one is rejected
+    double fb_lo = nan, fb_hi = nan;
+    const bool with_model = o.bounds_mode == CHESS_BOUNDS_LEARNED || o.bounds_mode == CHESS_BOUNDS_LEARNED_LANCZOS;
+    if (!given && with_model) {
         // predicted bounds widened by the model's margins (never beyond the
         // Gershgorin interval) and a predicted mu bracket; Eq. 6 and the
         // growth test still judge the bounds, bisection still judges mu
@@ -1759,11 +1796,22 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         const double w = 0.5 * (fe.g_hi - fe.g_lo);
         lo = std::max(fe.g_lo, pred[0] - M.margin_lo * w);
         hi = std::min(fe.g_hi, pred[1] + M.margin_hi * w);
+        fb_lo = fe.g_lo;
+        fb_hi = fe.g_hi;
+        if (o.bounds_mode == CHESS_BOUNDS_LEARNED_LANCZOS) {
+            // each side from whichever estimate is tighter there; the
+            // Lanczos interval alone is the fallback
+            chess_opts ol = o;
+            ol.bounds_mode = CHESS_BOUNDS_LANCZOS;
+            h_bounds(ctx, PH, F.Hp.as<double>(), ol, &fb_lo, &fb_hi);
+            lo = std::max(lo, fb_lo);
+            hi = std::min(hi, fb_hi);
+        }
         if (hi > lo) {
             learned = true;
         } else {
-            lo = fe.g_lo;
-            hi = fe.g_hi;
+            lo = fb_lo;
+            hi = fb_hi;
             fallback |= 1;
         }
         if (!br_given) {
@@ -1782,7 +1830,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     int n_pl = 0, reexp = 0, passes = 0;
     double penalty = std::numeric_limits<double>::quiet_NaN();
     double ms_chain = 0.0, kernel_ms = 0.0, kernel_ms_acc = 0.0;
-    int variant = -1;
+    int variant = -1, variant_moments = -1;
     bool have_hist = false;
     Timer tm(st);
     // Width check of Sec. "Fermi Operator Expansion" (adapt_kt): the chain
@@ -1840,15 +1888,17 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         ms_chain += tm.stop();
         kernel_ms += rq.kernel_ms;
         if (rq.nq > 0) kernel_ms_acc += rq.kernel_ms;
+        else variant_moments = rq.variant;
         variant = rq.variant;
         passes++;
         const hostmath::BoundsCheck chk = hostmath::bounds_check(mom, n);
         penalty = chk.penalty;
         if (chk.ok) break;
         if (learned) {
-            // predicted bounds rejected: fall back to the rigorous interval
-            lo = fe.g_lo;
-            hi = fe.g_hi;
+            // predicted bounds rejected: fall back to the Gershgorin (or,
+            // combined with Lanczos, the Lanczos) interval
+            lo = fb_lo;
+            hi = fb_hi;
             learned = false;
             fallback |= 1;
             reexp++;
@@ -1971,6 +2021,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         info->ms_post = t_end - t_post0;
         info->ms_chain_kernel = kernel_ms;
         info->ms_chain_kernel_acc = kernel_ms_acc;
+        info->kernel_variant_moments = variant_moments;
         info->kernel_variant = variant;
         info->pred_lo = pred[0];
         info->pred_hi = pred[1];
@@ -2328,7 +2379,8 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
         nes[s] = it.n_electrons;
         preds[s] = {nan, nan, nan};
         double mu_half = 0.0;
-        if (!(std::isfinite(o.bounds[0]) && std::isfinite(o.bounds[1])) && o.bounds_mode == CHESS_BOUNDS_LEARNED) {
+        if (!(std::isfinite(o.bounds[0]) && std::isfinite(o.bounds[1])) &&
+            (o.bounds_mode == CHESS_BOUNDS_LEARNED || o.bounds_mode == CHESS_BOUNDS_LEARNED_LANCZOS)) {
             Features fe;
             compute_features(ctx, PHs[s], Hp, PKs[s], slo[s], shi[s], it.n_electrons, it.kT, fe);
             double pr[3];
@@ -2336,6 +2388,14 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
             const double w = 0.5 * (fe.g_hi - fe.g_lo);
             lo[s] = std::max(fe.g_lo, pr[0] - ctx->model.margin_lo * w);
             hi[s] = std::min(fe.g_hi, pr[1] + ctx->model.margin_hi * w);
+            if (o.bounds_mode == CHESS_BOUNDS_LEARNED_LANCZOS) {
+                chess_opts ol = o;
+                ol.bounds_mode = CHESS_BOUNDS_LANCZOS;
+                double llo, lhi;
+                h_bounds(ctx, PHs[s], Hp, ol, &llo, &lhi);
+                lo[s] = std::max(lo[s], llo);
+                hi[s] = std::min(hi[s], lhi);
+            }
             if (!(hi[s] > lo[s])) {
                 lo[s] = fe.g_lo;
                 hi[s] = fe.g_hi;
@@ -2349,7 +2409,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
             double m = it.mu_trial[q];
             if (!std::isfinite(m)) {
                 if (!std::isfinite(preds[s][2]))
-                    CHESS_THROW(CHESS_E_ARG, "system %d: mu_trial[%d] not given and no prediction (CHESS_BOUNDS_LEARNED)", idx[s], q);
+                    CHESS_THROW(CHESS_E_ARG, "system %d: mu_trial[%d] not given and no prediction (learned bounds modes)", idx[s], q);
                 m = preds[s][2] + (q - 1) * mu_half;
             }
             mus[s][q] = m;

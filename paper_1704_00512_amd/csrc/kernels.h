@@ -51,7 +51,7 @@ struct Epilogue {
     double coef[4] = {0, 0, 0, 0};
     void *hist = nullptr;
     double *trace_partial = nullptr;
-    // batches of systems (listed kernel only): when row_sys is set, the
+    // batches of systems (listed and searching kernels): when row_sys is set, the
     // weight of accumulator q for a tile is coef_sys[q][row_sys[first row]]
     // (tiles never straddle systems) instead of coef[q]
     const int32_t *row_sys = nullptr;

@@ -169,18 +169,19 @@ __device__ inline void stage_tile(const ProductPlanDev &plan, const ProductOpera
 }
 
 // Epilogue for one output element (see Epilogue in kernels.h); the operands
-// read from memory were loaded ahead (prevv, accv).
+// read from memory were loaded ahead (prevv, accv); wq are the tile's weights
+// of the float64 sums.
 template <typename T>
 __device__ inline void store_output(const ProductOperands &ops, const Epilogue &ep, int64_t off,
-                                    T y, T prevv, const double (&accv)[4], bool diag,
-                                    double &tr) {
+                                    T y, T prevv, const double (&accv)[4], const double (&wq)[4],
+                                    bool diag, double &tr) {
     T o = (T)ep.alpha * y;
     if (ep.prev) o = fma((T)ep.beta, prevv, o);
     reinterpret_cast<T *>(ops.c_out)[off] = o;
     const double od = (double)o;
 #pragma unroll
     for (int qa = 0; qa < 4; ++qa)
-        if (qa < ep.nacc) ep.acc[qa][off] = accv[qa] + ep.coef[qa] * od;
+        if (qa < ep.nacc) ep.acc[qa][off] = accv[qa] + wq[qa] * od;
     if (ep.hist) reinterpret_cast<T *>(ep.hist)[off] = o;
     if (diag) tr += od;
 }
@@ -228,6 +229,15 @@ __global__ __launch_bounds__(64 * NW) void k_product(ProductPlanDev plan, Produc
     const int row0 = plan.tile_row0[tile];
     const int c = plan.tile_row0[tile + 1] - row0;
     stage_tile<T, B, CMAX, NT>(plan, ops, smem, L, tile, row0, c);
+    // weights of the float64 sums: in batches (row_sys set; tiles never
+    // straddle systems) those of the tile's system
+    double wq[4];
+    {
+        const int sys = ep.row_sys ? ep.row_sys[row0] : 0;
+#pragma unroll
+        for (int qa = 0; qa < 4; ++qa)
+            wq[qa] = (ep.row_sys && ep.coef_sys[qa]) ? ep.coef_sys[qa][sys] : ep.coef[qa];
+    }
 
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -477,7 +487,7 @@ __global__ __launch_bounds__(64 * NW) void k_product(ProductPlanDev plan, Produc
 #pragma unroll
         for (int q = 0; q < NE; ++q)
             if (valid[q])
-                store_output<T>(ops, ep, off[q], y[q], prevv[q], accv[q],
+                store_output<T>(ops, ep, off[q], y[q], prevv[q], accv[q], wq,
                                 row0 + ei[q] == j && er[q] == es[q], tr);
         // the next column overwrites this wave's staging and lists
         wave_lds_sync();

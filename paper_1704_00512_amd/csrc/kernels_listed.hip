@@ -1195,14 +1195,17 @@ __host__ __device__ inline Lean9Lds lean9_lds(const ListedPlanDev &p) {
 // column are loaded without branches, after the Bt loads of the column's last
 // hit group (vector memory loads complete in order, so loads issued earlier
 // would delay that group's MFMAs); Bt, hit lists and epilogue operands go
-// through buffer descriptors.  At most one float64 sum (MAXACC 0 or 1).
+// through buffer descriptors.  MAXACC 0 or 1: no sum, or one sum whose
+// operands are prefetched with the column's; MAXACC 4: up to four sums
+// (batches, matrix powers with two exponents), each read in the column's
+// epilogue, so that the pipelined state holds no sums.
 template <int NW, int MAXACC>
 __global__ __launch_bounds__(64 * NW) void k_lean9(ListedPlanDev plan, ProductOperands ops, Epilogue ep) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int BB = 81;
     constexpr int NT = 64 * NW;
     constexpr int kEntMax = kEntWords * 64 * 2;  // 2-byte entries in a wave's 1 KB
-    static_assert(MAXACC <= 1, "at most one float64 sum");
+    static_assert(MAXACC == 0 || MAXACC == 1 || MAXACC == 4, "zero, one or up to four float64 sums");
     const int ntiles = plan.ntiles;
     const int nt8 = (ntiles + 7) & ~7;
     const int w = blockIdx.x;
@@ -1246,10 +1249,12 @@ __global__ __launch_bounds__(64 * NW) void k_lean9(ListedPlanDev plan, ProductOp
     const uint32_t eo = (uint32_t)(3 * (slot / 3) * 9 + bcol);
     const float *BtV = reinterpret_cast<const float *>(ops.bt_val);
     const float *Prev = reinterpret_cast<const float *>(ep.prev);
-    double wq = 0.0;
+    double wq[4] = {0.0, 0.0, 0.0, 0.0};
     if (MAXACC > 0) {
         const int sys = ep.row_sys ? ep.row_sys[row0] : 0;
-        wq = (ep.row_sys && ep.coef_sys[0]) ? ep.coef_sys[0][sys] : ep.coef[0];
+#pragma unroll
+        for (int qa = 0; qa < MAXACC; ++qa)
+            wq[qa] = (ep.row_sys && ep.coef_sys[qa]) ? ep.coef_sys[qa][sys] : ep.coef[qa];
     }
     constexpr int kAll = 0x7FFFFFFF;
     auto rsrc = [](const void *p, int n) __attribute__((always_inline)) {
@@ -1258,10 +1263,13 @@ __global__ __launch_bounds__(64 * NW) void k_lean9(ListedPlanDev plan, ProductOp
     const __amdgpu_buffer_rsrc_t r_prev = rsrc(Prev ? ep.prev : ops.a_val, kAll);
     const __amdgpu_buffer_rsrc_t r_out = rsrc(ops.c_out, kAll);
     const __amdgpu_buffer_rsrc_t r_hist = rsrc(ep.hist ? ep.hist : ops.c_out, kAll);
-    const __amdgpu_buffer_rsrc_t r_acc = rsrc(MAXACC > 0 ? (const void *)ep.acc[0] : ops.c_out, kAll);
+    __amdgpu_buffer_rsrc_t r_acc[MAXACC > 0 ? MAXACC : 1];
+#pragma unroll
+    for (int qa = 0; qa < (MAXACC > 0 ? MAXACC : 1); ++qa)
+        r_acc[qa] = rsrc((MAXACC > 0 && qa < ep.nacc) ? (const void *)ep.acc[qa] : ops.c_out, kAll);
     const __amdgpu_buffer_rsrc_t r_ent = rsrc(plan.entries, kAll);
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    constexpr int NA = MAXACC > 0 ? 1 : 0;
+    constexpr int NA = MAXACC == 1 ? 1 : 0;  // sums prefetched with the column
     struct Set {
         i32x4 ra, rb;
         uint32_t ew[kEntWords];
@@ -1299,8 +1307,8 @@ __global__ __launch_bounds__(64 * NW) void k_lean9(ListedPlanDev plan, ProductOp
             for (int v = 0; v < 3; ++v) {
                 const uint32_t e = S.off[i] + v * 9;
                 S.prev[i][v] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r_prev, (int)(e * 4), 0, 0));
-                if constexpr (MAXACC > 0)
-                    S.acc[i][v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r_acc, (int)(e * 8), 0, 0));
+                if constexpr (MAXACC == 1)
+                    S.acc[i][v] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r_acc[0], (int)(e * 8), 0, 0));
             }
     };
     double tr = 0.0;
@@ -1391,10 +1399,19 @@ __global__ __launch_bounds__(64 * NW) void k_lean9(ListedPlanDev plan, ProductOp
                 if (Prev) o = fmaf((float)ep.beta, C.prev[i][v], o);
                 __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, o), r_out, (int)(e * 4), 0, 0);
                 const double od = (double)o;
-                if constexpr (MAXACC > 0)
+                if constexpr (MAXACC == 1)
                     if (ep.nacc > 0)
-                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, C.acc[i][v] + wq * od), r_acc,
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, C.acc[i][v] + wq[0] * od), r_acc[0],
                                                               (int)(e * 8), 0, 0);
+                if constexpr (MAXACC > 1) {
+#pragma unroll
+                    for (int qa = 0; qa < MAXACC; ++qa)
+                        if (qa < ep.nacc) {
+                            const double a = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r_acc[qa], (int)(e * 8), 0, 0));
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, a + wq[qa] * od), r_acc[qa],
+                                                                  (int)(e * 8), 0, 0);
+                        }
+                }
                 if (ep.hist) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, o), r_hist, (int)(e * 4), 0, 0);
                 if (row0 + i == jc && 3 * (slot / 3) + v == bcol) tr += od;
             }
@@ -1427,9 +1444,8 @@ hipError_t launch_lean9(const ListedPlanDev &plan, const ProductOperands &ops, c
         return hipSuccess;
     }
     if (plan.ntiles == 0) return hipSuccess;
-    if (ep.nacc > 1) return launch_9<NW, 1, 4>(plan, ops, ep, st, lds_out);  // more sums: k_listed9
     if (plan.entry_width != 1 || plan.cmax != 2 || !plan.off31) return hipErrorInvalidValue;
-    const void *fn = ep.nacc == 1 ? (const void *)k_lean9<NW, 1> : (const void *)k_lean9<NW, 0>;
+    if (ep.nacc > 4) return hipErrorInvalidValue;
     static int raised_device = -1;
     static size_t raised_to = 0;
     int dev = 0;
@@ -1438,13 +1454,16 @@ hipError_t launch_lean9(const ListedPlanDev &plan, const ProductOperands &ops, c
         hipError_t e = hipFuncSetAttribute((const void *)k_lean9<NW, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void *)k_lean9<NW, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)k_lean9<NW, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         raised_device = dev;
         raised_to = lds;
     }
-    (void)fn;
     const int nt8 = (plan.ntiles + 7) & ~7;
-    if (ep.nacc == 1)
+    if (ep.nacc > 1)
+        hipLaunchKernelGGL((k_lean9<NW, 4>), dim3(nt8), dim3(64 * NW), lds, st, plan, ops, ep);
+    else if (ep.nacc == 1)
         hipLaunchKernelGGL((k_lean9<NW, 1>), dim3(nt8), dim3(64 * NW), lds, st, plan, ops, ep);
     else
         hipLaunchKernelGGL((k_lean9<NW, 0>), dim3(nt8), dim3(64 * NW), lds, st, plan, ops, ep);

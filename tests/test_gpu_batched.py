@@ -148,3 +148,32 @@ def test_batched_forced_kernel_variants(gpu_ctx, monkeypatch, variant, which):
                                        h_bounds=(inf["lo"], inf["hi"]), n_pl=inf["n_pl"],
                                        mu=a["mu_trial"][q])
             assert np.max(np.abs(r["K"][q].cpu().numpy() - Ko)) < 1e-5, (variant, s.n, q)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_batched_long_rows_use_the_searching_product(gpu_ctx, precision, tol):
+    # a dense 150-atom system (H rows of 150 blocks, longer than the hit-list
+    # format's 128) batched with an ordinary one: the chain runs on the
+    # searching product, with tiles that never straddle the two systems and
+    # each system's own weights for its three sums
+    key = "long-rows"
+    if key not in _sys:
+        print("[batched] dense system atoms=150 b=4 (all pairs within the cutoffs)", flush=True)
+        _sys[key] = [g.make_system(150, 4, 40.0, 40.0, seed=36, kT=0.02), systems()[0]]
+    ss = _sys[key]
+    assert np.max(np.diff(ss[0].pat_h.row_ptr)) > 128
+    args = batch_args(ss)
+    res = chess_fermi_operator_batched(gpu_ctx, args, precision=precision, bounds_mode="lanczos")
+    for s, a, r in zip(ss, args, res):
+        inf = r["info"]
+        sb, hb = (inf["s_lo"], inf["s_hi"]), (inf["lo"], inf["hi"])
+        H, S, P = bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k)
+        X, _ = opl.matrix_power(S, -0.5, P, bounds=sb, n_pl=inf["n_pl_s"])
+        assert np.max(np.abs(r["Sinvhalf"].cpu().numpy() - X)) < tol
+        for q in range(3):
+            Ko, _ = opl.fermi_operator(H, S, P, s.n_electrons, s.kT, s_bounds_=sb,
+                                       n_pl_s=inf["n_pl_s"], h_bounds=hb, n_pl=inf["n_pl"],
+                                       mu=a["mu_trial"][q])
+            err = float(np.max(np.abs(r["K"][q].cpu().numpy() - Ko)))
+            print(f"[batched] long rows {precision}: system n={s.n} K[{q}] err {err:.2e}", flush=True)
+            assert err < tol, (s.n, q)

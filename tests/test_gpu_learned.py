@@ -152,3 +152,32 @@ def test_learned_predictor_gain_on_held_out_systems():
     assert np.mean(ratios) > 1.5
     assert np.mean(bis_l) < np.mean(bis_g)
     assert fallbacks <= 2
+
+
+def test_learned_lanczos_bounds_are_the_intersection(gpu_ctx):
+    """CHESS_BOUNDS_LEARNED_LANCZOS: each side from the tighter of the
+    predictor's interval and the Lanczos one (when neither is rejected), and
+    the result that of the Lanczos form."""
+    chess_model_load(gpu_ctx, np.load(MODEL))
+    for i in range(3):
+        s = g.predictor_system(g.PREDICTOR_TEST_SEED0 + 2000 + i)
+        print(f"[learned] intersection, seed {g.PREDICTOR_TEST_SEED0 + 2000 + i} n={s.n}", flush=True)
+        dv = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+        ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx)
+        pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx)
+        H, S = dv(s.H), dv(s.S)
+        common = dict(precision="f64", tol_fit=1e-10, store_history=1)
+        run = lambda mode: chess_fermi_operator(gpu_ctx, H, ph, S, ph, pk, s.n_electrons, s.kT,
+                                                bounds_mode=mode, **common)
+        K_lz, i_lz = run("lanczos")
+        _, i_le = run("learned")
+        K_ll, i_ll = run("learned_lanczos")
+        assert i_lz["reexpansions"] == 0
+        if i_le["fallback"] & 1 == 0 and i_ll["fallback"] & 1 == 0 and i_ll["reexpansions"] == 0:
+            assert i_ll["lo"] == max(i_le["lo"], i_lz["lo"])
+            assert i_ll["hi"] == min(i_le["hi"], i_lz["hi"])
+        assert i_ll["pred_mu"] == i_le["pred_mu"]
+        # two converged expansions on different intervals: after truncation to
+        # the pattern their K differ by ~1e-7 (as for learned vs Gershgorin)
+        assert abs(i_ll["mu"] - i_lz["mu"]) < 1e-7
+        assert np.max(np.abs(K_ll.cpu().numpy() - K_lz.cpu().numpy())) < 1e-6

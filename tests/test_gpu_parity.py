@@ -161,10 +161,11 @@ def test_chain_kernel_long_hit_lists(gpu_ctx, monkeypatch, variant):
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
-@pytest.mark.parametrize("nq", [1, 2])
+@pytest.mark.parametrize("nq", [1, 2, 4])
 def test_b9_chain_kernel_variants(gpu_ctx, monkeypatch, variant, nq):
     # float32 9 x 9 blocks: vector ALU (0), matrix cores (1, 2) and pipelined
-    # columns (3, 4; two sums fall back to 1, 2), against the oracle
+    # columns (3, 4; with more than one sum each is read in the column's
+    # epilogue), against the oracle
     monkeypatch.setenv("CHESS_LISTED_VARIANT", str(variant))
     s, accs, mom, acc_o, mom_o = chain_case(gpu_ctx, SYS9, 70, "f32", nq=nq)
     assert np.max(np.abs(mom - mom_o)) < TOL32 * s.n
