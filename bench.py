@@ -11,13 +11,14 @@ Printed JSON line:
                bytes of every chain-product launch in the timed steps divided
                by their device time (HIP events on the library's stream);
   ms_per_step  density-kernel time to solution of the timed form (float32
-               chain, bounds from the learned predictor - or Lanczos with
-               --form lanczos - checked by Eq. 6, tol_fit 1e-6);
+               chain, tol_fit 1e-6, bounds checked by Eq. 6): by default the
+               learned predictor's mu bracket and its interval intersected
+               with the Lanczos one (--form picks another bounds mode);
   roofline     the chain product kernel against MI355X peaks, the call as a
                whole and each pass (moments only / accumulating) on its own;
   reference_f64  K from the float64 chain with Lanczos bounds and tol_fit
                1e-10; every form's K is compared with it (max_abs_err_vs_ref);
-  form_*_f32   the other float32 form (Lanczos or learned), untimed;
+  form_*_f32   the other float32 forms (Lanczos, predictor alone), untimed;
   eigs_window  eigenvalues in [mu - 0.05, mu + 0.05] Ha from one float32
                chain's moments;
   cpu_baseline the oracle's chain (plain C, float64) on a bounded sample of
@@ -86,16 +87,73 @@ def kernel_source_hash():
 
 def measured_traffic(workload):
     """HBM bytes per chain launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source."""
+    if it was taken on the current kernel source: (average over the call's
+    launches, {pass: bytes per launch of that pass}), or (None, {})."""
     path = os.path.join(ROOT, "profiles", f"chain_product_traffic_{workload}.md")
     if not os.path.exists(path):
-        return None
+        return None, {}
     text = open(path).read()
     m = re.search(r"kernel_source_sha1:\s*(\w+)", text)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m or not t or m.group(1) != kernel_source_hash():
-        return None
-    return float(t.group(1))
+        return None, {}
+    per = {k: float(v) for k, v in re.findall(r"hbm_bytes_per_launch_(\w+):\s*([0-9.eE+]+)", text)}
+    return float(t.group(1)), per
+
+
+def precision_table():
+    """The precision study: K (fixed bounds, degree and mu taken from a float64
+    call) and S^-1/2 in each precision, max-abs against the float64 path (whose
+    parity with the oracle the full-size tests check on sampled columns), and
+    each precision's average chain launch against its roof."""
+    import numpy as np
+    import torch
+    from paper_1704_00512_amd import BlockPattern, Context, chess_fermi_operator, chess_matrix_power
+    from workloads.generator import make_config
+    out = {}
+    ctx = Context(0)
+    dev = torch.device("cuda:0")
+    for wl, precs in (("prec9000", ("f64", "f32")),
+                      ("prec9000b4", ("f64", "f32", "bf16x3", "bf16"))):
+        log(f"precision table: {wl}")
+        sysm = make_config(wl)
+        H = torch.tensor(sysm.H, device=dev)
+        S = torch.tensor(sysm.S, device=dev)
+        ph = BlockPattern.from_host(sysm.b, sysm.pat_h.row_ptr, sysm.pat_h.col_idx, dev)
+        pk = BlockPattern.from_host(sysm.b, sysm.pat_k.row_ptr, sysm.pat_k.col_idx, dev)
+        K64, i64 = chess_fermi_operator(ctx, H, ph, S, ph, pk, sysm.n_electrons, sysm.kT,
+                                        precision="f64", bounds_mode="lanczos", tol_fit=1e-10,
+                                        tol_fit_s=1e-12, store_history=0)
+        fixed = dict(bounds=(i64["lo"], i64["hi"]), n_pl=i64["n_pl"],
+                     s_bounds=(i64["s_lo"], i64["s_hi"]), n_pl_s=i64["n_pl_s"], mu=i64["mu"])
+        X64, _ = chess_matrix_power(ctx, S, ph, -0.5, pk, precision="f64", s_bounds=fixed["s_bounds"],
+                                    n_pl_s=fixed["n_pl_s"])
+        K64, X64 = K64.cpu().numpy(), X64.cpu().numpy()
+        steps = max(fixed["n_pl"] - 2, 1)
+        rows = {}
+        for p in precs:
+            K, ik = chess_fermi_operator(ctx, H, ph, S, ph, pk, sysm.n_electrons, sysm.kT,
+                                         precision=p, store_history=0, **fixed)
+            X, _ = chess_matrix_power(ctx, S, ph, -0.5, pk, precision=p, s_bounds=fixed["s_bounds"],
+                                      n_pl_s=fixed["n_pl_s"])
+            ms_l = ik["ms_chain_kernel"] / steps
+            vb = 8 if p == "f64" else 4
+            byts = chain_step_cost(sysm, vb, 1, False)
+            if p.startswith("bf16"):  # H~ read as bfloat16 (hi, and lo for bf16x3)
+                nh = sysm.pat_h.nnzb * sysm.b * sysm.b
+                byts += nh * ((4 if p == "bf16x3" else 2) - 4)
+            gbs = byts / (ms_l * 1e-3) / 1e9
+            rows[p] = dict(max_abs_err_K=float(np.max(np.abs(K.cpu().numpy() - K64))),
+                           max_abs_err_Sinvhalf=float(np.max(np.abs(X.cpu().numpy() - X64))),
+                           chain_launch_ms=round(ms_l, 4), kernel_variant=ik["kernel_variant"],
+                           algorithmic_gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+            log(f"  {p}: K {rows[p]['max_abs_err_K']:.2e}, S^-1/2 {rows[p]['max_abs_err_Sinvhalf']:.2e}, "
+                f"{ms_l:.4f} ms per launch")
+        out[wl] = dict(rows=sysm.n, b=sysm.b, nnzb_h=int(sysm.pat_h.nnzb), nnzb_k=int(sysm.pat_k.nnzb),
+                       kT=sysm.kT, n_pl=fixed["n_pl"], n_pl_s=fixed["n_pl_s"], mu=fixed["mu"],
+                       reference="float64 path, Lanczos bounds, tol_fit 1e-10", precisions=rows)
+    ctx.close()
+    return out
 
 
 def cpu_baseline(sysm, budget_s=20.0):
@@ -240,11 +298,16 @@ def main():
                     help="only run one N_PL-term chain (one accumulator) on the workload's H, "
                          "for counter collection")
     ap.add_argument("--precision", default="f32", help="--chain-only: f32, f64, bf16 or bf16x3")
-    ap.add_argument("--form", default="learned", choices=("learned", "lanczos", "gershgorin"),
-                    help="bounds of the timed float32 form (learned: the loaded predictor)")
+    ap.add_argument("--form", default="learned_lanczos",
+                    choices=("learned_lanczos", "learned", "lanczos", "gershgorin"),
+                    help="bounds of the timed float32 form (learned*: the loaded predictor)")
     ap.add_argument("--no-ref", action="store_true", help="skip the float64 reference K")
-    ap.add_argument("--no-other", action="store_true", help="skip the other float32 form")
+    ap.add_argument("--no-other", action="store_true", help="skip the other float32 forms")
     ap.add_argument("--no-eigs", action="store_true", help="skip the eigenvalue window")
+    ap.add_argument("--precision-table", action="store_true",
+                    help="only the precision study: K and S^-1/2 in every precision against "
+                         "the float64 path on the 9000-row workloads (b = 9, and b = 4 for "
+                         "the bfloat16 forms), one JSON line")
     ap.add_argument("--variant", type=int, default=-1,
                     help="--chain-only: force this chain-kernel variant (CHESS_LISTED_VARIANT)")
     args = ap.parse_args()
@@ -281,6 +344,10 @@ def main():
         ctx.close()
         return
 
+    if args.precision_table:
+        print(json.dumps(precision_table()), flush=True)
+        return
+
     if args.calibrate_copy:
         n = 1 << 28  # 2^28 float32 = 1 GiB read + 1 GiB written per copy
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -312,7 +379,7 @@ def main():
     if have_model:
         chess_model_load(ctx, np.load(model_path))
     form = args.form
-    if form == "learned" and not have_model:
+    if form.startswith("learned") and not have_model:
         log("no predictor model: the timed form falls back to Lanczos bounds")
         form = "lanczos"
     tol_fit, tol_fit_s = 1e-6, 1e-7
@@ -358,7 +425,7 @@ def main():
     t_hbm = bytes_call / (HBM_PEAK_GBS * 1e9)
     t_alu = flops_launch * launches_call / (FP32_PEAK_TFLOPS * 1e12)
     avg_launch_ms = kern_ms / max(launches_call, 1)
-    traffic = measured_traffic(args.workload)
+    traffic, traffic_pass = measured_traffic(args.workload)
     # each pass against its own roof: the moments pass (no float64 sum) and
     # the accumulating pass, from the library's per-pass device times
     per_pass = []
@@ -384,11 +451,19 @@ def main():
     else:
         roof = dict(bound="mfma", achieved=round(tflops, 2), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=round(tflops / FP32_PEAK_TFLOPS, 4))
-    v = info["kernel_variant"]
-    kname = ("k_stat<float32> (output-stationary chain product)" if 24 <= v <= 26 else
-             "k_lean<...> (chain product, MFMA slots shared among tile rows)" if 16 <= v <= 23 else
-             "k_listed<float,4,4,...> (chain product)")
-    roof.update(traffic=traffic, kernel=f"{kname}, variant {v} chosen by timing",
+    def kname(v):
+        return ("k_stat<float32> (output-stationary chain product)" if 24 <= v <= 26 else
+                "k_lean<...> (chain product, MFMA slots shared among tile rows)" if 16 <= v <= 23 else
+                "k_listed<float,4,4,...> (chain product)")
+    v, vm = info["kernel_variant"], info["kernel_variant_moments"]
+    for d in per_pass:
+        pv = vm if d["pass_"] == "moments" else v
+        d["kernel"] = f"{kname(pv)}, variant {pv}"
+        d["traffic"] = traffic_pass.get(d["pass_"])
+    kdesc = (f"{kname(v)}, variant {v} chosen by timing" if vm in (v, -1) else
+             f"moments pass {kname(vm)} (variant {vm}), accumulating pass {kname(v)} (variant {v}), "
+             "each chosen by timing")
+    roof.update(traffic=traffic, kernel=kdesc,
                 avg_launch_ms=round(avg_launch_ms, 4),
                 algorithmic_bytes_per_call=int(bytes_call), launches_per_call=launches_call,
                 flops_per_launch=flops_launch, achieved_gbs=round(gbs, 1),
@@ -398,6 +473,8 @@ def main():
                 kernel_source_sha1=kernel_source_hash())
 
     form_name = {"lanczos": "Lanczos bounds", "learned": "learned bounds and mu bracket (predictor)",
+                 "learned_lanczos": "learned mu bracket, predictor interval intersected with the "
+                                    "Lanczos one",
                  "gershgorin": "Gershgorin bounds"}[form]
     out = dict(metric=METRIC, value=round(gbs, 1), unit="GB/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_per_step, 2), higher_is_better=True,
@@ -439,9 +516,14 @@ def main():
         err = float(np.max(np.abs(K_fast - K_ref)))
         out["config"]["max_abs_err_vs_ref"] = err
         log(f"reference f64: {rms:.0f} ms n_pl={rinfo['n_pl']}; max|K_fast - K_ref| = {err:.2e}")
-    # the other single-precision form (learned <-> Lanczos), untimed
-    other = "lanczos" if form == "learned" else ("learned" if have_model else None)
-    if other and not args.no_other:
+    # the other single-precision forms (Lanczos, the predictor alone), untimed
+    out["config"]["bisect_iters"] = info["bisect_iters"]
+    out["config"]["bounds"] = [info["lo"], info["hi"]]
+    if form.startswith("learned"):
+        out["config"]["fallback"] = info["fallback"]
+        out["config"]["pred"] = [info["pred_lo"], info["pred_hi"], info["pred_mu"]]
+    others = [m for m in ("lanczos", "learned") if m != form and (m == "lanczos" or have_model)]
+    for other in ([] if args.no_other else others):
         oinfo, oms, K_o = run_form(other, dict(fast, bounds_mode=other))
         rec = dict(ms=round(oms, 1), n_pl=oinfo["n_pl"], passes=oinfo["passes"],
                    bounds=[oinfo["lo"], oinfo["hi"]], mu=oinfo["mu"],
@@ -450,10 +532,6 @@ def main():
         if K_ref is not None:
             rec["max_abs_err_vs_ref"] = float(np.max(np.abs(K_o - K_ref)))
         out[f"form_{other}_f32"] = rec
-        out["config"]["bisect_iters"] = info["bisect_iters"]
-        if form == "learned":
-            out["config"]["fallback"] = info["fallback"]
-            out["config"]["pred"] = [info["pred_lo"], info["pred_hi"], info["pred_mu"]]
         log(f"{other}: {oms:.0f} ms n_pl={oinfo['n_pl']} bisect={oinfo['bisect_iters']}")
     if not args.no_eigs:
         # eigenvalues in [mu - 0.05, mu + 0.05] Ha (Sec. "Extraction of selected

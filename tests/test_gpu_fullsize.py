@@ -7,7 +7,10 @@ single columns at any size).
             chain in the benchmark's launch configuration (kernel variant
             chosen by timing);
   prec9000: 9 000 rows, b = 9 - S^-1/2 in float64 and float32 (the precision
-            study), and the chain on H.
+            study), and the chain on H;
+  prec9000b4: the same 9 000 rows and neighbours with 4 x 4 blocks (2250
+            atoms) - the chain and S^-1/2 in all four precisions, the
+            bfloat16 operand forms included (they need b = 4).
 """
 import numpy as np
 import pytest
@@ -112,11 +115,30 @@ def test_prec9000_chain_sampled_columns(gpu_ctx, precision, tol):
 
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_prec9000_inverse_sqrt_sampled_columns(gpu_ctx, precision, tol):
-    s = workload("prec9000")
+    inverse_sqrt_check(gpu_ctx, "prec9000", precision, tol)
+
+
+# bfloat16 bars: bf16x3 the 1e-3 of the bfloat16 target; plain bf16 (8
+# significant bits per operand) the 2e-2 its rounding gives
+PREC_B4 = [("f64", 1e-10), ("f32", 1e-5), ("bf16x3", 1e-3), ("bf16", 2e-2)]
+
+
+@pytest.mark.parametrize("precision,tol", PREC_B4)
+def test_prec9000b4_chain_sampled_columns(gpu_ctx, precision, tol):
+    chain_check(gpu_ctx, "prec9000b4", precision, tol, 70, -3.0, 0.5, 16)
+
+
+@pytest.mark.parametrize("precision,tol", PREC_B4)
+def test_prec9000b4_inverse_sqrt_sampled_columns(gpu_ctx, precision, tol):
+    inverse_sqrt_check(gpu_ctx, "prec9000b4", precision, tol)
+
+
+def inverse_sqrt_check(gpu_ctx, name, precision, tol):
+    s = workload(name)
     dev = torch.device("cuda")
     ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx, dev)
     pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx, dev)
-    print(f"[fullsize] prec9000 {precision} S^-1/2 on the GPU", flush=True)
+    print(f"[fullsize] {name} {precision} S^-1/2 on the GPU", flush=True)
     R, info = chess_matrix_power(gpu_ctx, torch.tensor(s.S, device=dev), ph, -0.5, pk,
                                  precision=precision)
     lo, hi, n_pl = info["lo"], info["hi"], info["n_pl"]
@@ -124,6 +146,6 @@ def test_prec9000_inverse_sqrt_sampled_columns(gpu_ctx, precision, tol):
     S = opl.BlockMat(s.pat_h.nb, s.b, s.pat_h.row_ptr, s.pat_h.col_idx, s.S)
     cols = np.sort(np.random.default_rng(12).choice(s.n, size=16, replace=False))
     worst = max_column_error(s, [R.cpu().numpy()], opl.scaled(S.csr(), lo, hi), n_pl, coefs, cols)
-    print(f"[fullsize] prec9000 {precision} S^-1/2 (bounds [{lo:.4f}, {hi:.4f}], n_pl {n_pl}): "
+    print(f"[fullsize] {name} {precision} S^-1/2 (bounds [{lo:.4f}, {hi:.4f}], n_pl {n_pl}): "
           f"max |GPU - oracle| over 16 columns = {worst:.3e}", flush=True)
     assert worst < tol

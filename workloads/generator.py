@@ -308,6 +308,10 @@ CONFIGS = {
     "prec9000": dict(n_atoms=1000, b=9, r_h=4.57, r_k=5.99, seed=1, kT=0.005),
     # 20000 atoms x 4 -> 80000 rows; kernel pattern ~1 % (~64 M values).
     "large80k": dict(n_atoms=20000, b=4, r_h=5.59, r_k=7.82, seed=5, kT=0.003),
+    # 2250 atoms x 4 -> 9000 rows with the cutoffs of prec9000 (the same
+    # neighbours per atom): the 4 x 4-block stand-in of the precision study,
+    # for the bfloat16 operand forms, which need b = 4.
+    "prec9000b4": dict(n_atoms=2250, b=4, r_h=4.57, r_k=5.99, seed=1, kT=0.005),
 }
 
 
