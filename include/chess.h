@@ -195,6 +195,11 @@ typedef struct {
     /* chess_fermi_operator: chain kernel variant of the moments-only passes
      * (kernel_variant is that of the last pass; -1 if there was none) */
     int32_t kernel_variant_moments;
+    /* chess_fermi_operator: rows per tile of the H~' chain's plan (b = 4: 4 or
+     * 2, chosen by timing on the first chain over a pattern, or forced by
+     * CHESS_TILE_ROWS = 1, 2 or 4 in the environment; 0 for the searching
+     * kernel) */
+    int32_t tile_rows;
 } chess_info;
 
 /*

@@ -142,10 +142,12 @@ struct ProductPlan {
 struct ListedPlan {
     const Pattern *a = nullptr, *bt = nullptr, *c = nullptr;
     int dtype = 0;
+    int cmax = 0;         // rows per tile (at most)
     bool usable = false;  // false: rows too long for the list format
     // fastest kernel variant per operand mode, for passes without and with
     // float64 sums (-1: not timed yet)
     int tuned_variant[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
+    double tuned_ms[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};  // its time per product
     std::vector<int32_t> breaks;     // rows where a tile must start (batches: system starts)
     std::vector<int32_t> tile_row0;  // host copy, ntiles + 1
     ListedPlanDev dev;
@@ -172,6 +174,15 @@ struct chess_ctx {
     std::vector<std::unique_ptr<chess::EmbedMap>> embeds;
     std::vector<std::unique_ptr<chess::ProductPlan>> plans;
     std::vector<std::unique_ptr<chess::ListedPlan>> lplans;
+    // tile heights chosen by timing, per (A, Bt, storage, system breaks,
+    // operand mode, pass with or without float64 sums)
+    struct TileChoice {
+        const chess::Pattern *a, *bt;
+        int dtype;
+        std::vector<int32_t> breaks;
+        int opmode, pass, rows;
+    };
+    std::vector<TileChoice> tile_choices;
     chess_progress_fn progress = nullptr;
     void *progress_user = nullptr;
     int32_t progress_every = 0;
@@ -590,20 +601,22 @@ static void build_stat_groups(chess_ctx *ctx, ListedPlan *P) {
 // long for the list format; callers then use the searching kernel.
 static ListedPlan *get_listed_plan(chess_ctx *ctx, const Pattern *A, const Pattern *Bt,
                                    const Pattern *C, int dtype,
-                                   const std::vector<int32_t> &breaks = {}) {
+                                   const std::vector<int32_t> &breaks = {}, int rows = 0) {
+    const int cmax = rows > 0 ? rows : pick_cmax(dtype, A->b);
     for (auto &e : ctx->lplans)
-        if (e->a == A && e->bt == Bt && e->c == C && e->dtype == dtype && e->breaks == breaks) return e.get();
+        if (e->a == A && e->bt == Bt && e->c == C && e->dtype == dtype && e->breaks == breaks && e->cmax == cmax)
+            return e.get();
     auto P = std::make_unique<ListedPlan>();
     P->a = A;
     P->bt = Bt;
     P->c = C;
     P->dtype = dtype;
+    P->cmax = cmax;
     P->breaks = breaks;
     std::vector<char> is_break((size_t)A->nb + 1, 0);
     for (int32_t r : breaks)
         if (r >= 0 && r <= A->nb) is_break[r] = 1;
     const int b = A->b;
-    const int cmax = pick_cmax(dtype, b);
     const int ew = (A->max_row <= 255 && Bt->max_row <= 255) ? 1 : 2;
     const int max_col_entries = ew == 1 ? 512 : 256;  // LDS list area of a wave: 1 KB
     if (A->max_row > 65535 || Bt->max_row > 65535 || (b == 4 && Bt->max_row > 128) ||
@@ -1012,6 +1025,7 @@ struct ChainRequest {
     const char *label = "chain";  // stage name given to the progress callback
     double kernel_ms = 0.0;  // out: device time of the product launches
     int variant = -1;        // out: kernel variant of the listed product (-1: searching kernel)
+    int tile_rows = 0;       // out: rows per tile of the listed product's plan
 };
 
 // Kernel variant of a listed plan.  CHESS_LISTED_VARIANT=<v> in the
@@ -1057,6 +1071,11 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
         if (!fits(kStatVariantF32))
             CHESS_THROW(CHESS_E_UNSUPPORTED, "bfloat16 operands need b = 4 and rows of at most 254 blocks");
         lp->dev.variant = kStatVariantF32;
+    } else if (b == 4 && lp->cmax != 4) {
+        // tiles of other heights: the output-stationary kernel only
+        const int v = dtype == 1 ? kStatVariantF32 : kStatVariantF64 + 2;
+        if (!fits(v)) CHESS_THROW(CHESS_E_UNSUPPORTED, "tiles of %d rows need the output-stationary kernel", lp->cmax);
+        lp->dev.variant = v;
     } else if (nvar == 1)
         lp->dev.variant = 0;
     else if (b == 4 && dtype == 1)
@@ -1106,7 +1125,55 @@ static void select_listed_variant(chess_ctx *ctx, ListedPlan *lp, int dtype, int
     }
     if (best_v < 0) best_v = lp->dev.variant;
     lp->tuned_variant[opmode][pass] = best_v;
+    lp->tuned_ms[opmode][pass] = best_v >= 0 ? best / 3 : -1.0;
     lp->dev.variant = best_v;
+}
+
+// Row-tile height of a chain's plan (b = 4): the plan with the default 4-row
+// tiles against one with 2-row tiles (twice the workgroups, each row of Bt
+// read by twice the tiles; the output-stationary kernel only), each with its
+// fastest variant, on the chain's first product; the 2-row plan is kept for
+// the pattern and pass type when it is at least 3 % faster (both plans stay
+// cached).  CHESS_TILE_ROWS in the environment forces a height.  Returns the
+// plan to use (its variant set).
+static ListedPlan *tune_tile_rows(chess_ctx *ctx, ListedPlan *lp, int dtype, int n_pl,
+                                  const void *a, const void *bt, const void *prev, int opmode,
+                                  const void *bt_hi, const void *bt_lo, int nacc, double *const *acc) {
+    const Pattern *A = lp->a, *Bt = lp->bt, *C = lp->c;
+    auto pick = [&](ListedPlan *p) {
+        select_listed_variant(ctx, p, dtype, n_pl, a, bt, prev, opmode, bt_hi, bt_lo, nacc, acc);
+        return p;
+    };
+    auto stat_ready = [&](ListedPlan *p) {
+        const int v0 = dtype == 0 ? kStatVariantF64 : kStatVariantF32;
+        return p->usable && listed_product_variant_ok(dtype, 4, p->dev, v0, opmode);
+    };
+    if (A->b != 4) return pick(lp);
+    if (const char *env = std::getenv("CHESS_TILE_ROWS")) {
+        const int rows = std::atoi(env);
+        if (rows != 1 && rows != 2 && rows != 4) CHESS_THROW(CHESS_E_ARG, "CHESS_TILE_ROWS=%s: 1, 2 or 4 rows", env);
+        if (rows == lp->cmax) return pick(lp);
+        ListedPlan *alt = get_listed_plan(ctx, A, Bt, C, dtype, lp->breaks, rows);
+        if (!stat_ready(alt)) CHESS_THROW(CHESS_E_UNSUPPORTED, "CHESS_TILE_ROWS=%d: no output-stationary plan", rows);
+        return pick(alt);
+    }
+    const int pass = nacc > 0 ? 1 : 0;
+    for (const auto &tc : ctx->tile_choices)
+        if (tc.a == A && tc.bt == Bt && tc.dtype == dtype && tc.breaks == lp->breaks && tc.opmode == opmode &&
+            tc.pass == pass)
+            return pick(tc.rows == lp->cmax ? lp : get_listed_plan(ctx, A, Bt, C, dtype, lp->breaks, tc.rows));
+    pick(lp);
+    const double t4 = lp->tuned_ms[opmode][pass];
+    if (n_pl < 64 || t4 <= 0.0 || !stat_ready(lp)) return lp;  // too short to time, or untimed
+    ListedPlan *alt = get_listed_plan(ctx, A, Bt, C, dtype, lp->breaks, 2);
+    int rows = lp->cmax;
+    if (stat_ready(alt)) {
+        pick(alt);
+        const double t2 = alt->tuned_ms[opmode][pass];
+        if (t2 > 0.0 && t2 < 0.97 * t4) rows = 2;
+    }
+    ctx->tile_choices.push_back({A, Bt, dtype, lp->breaks, opmode, pass, rows});
+    return rows != lp->cmax ? alt : pick(lp);
 }
 
 // Runs T_0 .. T_{n_pl-1} in transposed storage U_k = T_k^T (see kernels.hip).
@@ -1141,9 +1208,10 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     if (rq.n_pl > 1)
         HIPCHECK(launch_scatter_blocks(dtype, b, PM->nnzb, emb->d_map_t.as<int64_t>(), rq.Mt, U1.p, 1, st));
     if (lplan->usable) {
-        select_listed_variant(ctx, lplan, dtype, rq.n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p, rq.nq,
-                              rq.acc);
+        lplan = tune_tile_rows(ctx, lplan, dtype, rq.n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p, rq.nq,
+                               rq.acc);
         rq.variant = lplan->dev.variant;
+        rq.tile_rows = lplan->cmax;
     }
     for (int q = 0; q < rq.nq; ++q) {
         const double *c = rq.coef + (size_t)q * rq.n_pl;
@@ -1218,6 +1286,9 @@ struct BatchChain {
     double *acc[4] = {nullptr, nullptr, nullptr, nullptr};
     const std::vector<int32_t> *row0 = nullptr;
     const int32_t *d_row_sys = nullptr;
+    // each system's own number of terms (n_pl is their maximum): a system's
+    // tiles stop once its chain is complete
+    const std::vector<int> *sys_npl = nullptr;
     bool use_graph = true;
     std::vector<double> *moments = nullptr;
     double kernel_ms = 0.0;
@@ -1256,7 +1327,7 @@ static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
                                    rq.opmode == kStatBF16X3 ? Blo.as<unsigned short>() : nullptr, st));
     }
     if (lp->usable) {
-        select_listed_variant(ctx, lp, dtype, n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p, rq.nq, rq.acc);
+        lp = tune_tile_rows(ctx, lp, dtype, n_pl, U1.p, Bt.p, U0.p, rq.opmode, Bhi.p, Blo.p, rq.nq, rq.acc);
         rq.variant = lp->dev.variant;
     } else {
         rq.variant = -1;
@@ -1287,6 +1358,13 @@ static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
     }
     DevBuf dseg;
     upload(dseg, seg, st);
+    // the last step k (product T_{k+1}) each system needs: n_pl(s) - 2
+    DevBuf dlast;
+    if (rq.sys_npl) {
+        std::vector<int32_t> last(nsys);
+        for (int sy = 0; sy < nsys; ++sy) last[sy] = (*rq.sys_npl)[sy] - 2;
+        upload(dlast, last, st);
+    }
     DevBuf part(sizeof(double) * (size_t)std::max(n_pl, 2) * std::max(ntiles, 256));
     DevBuf mom(sizeof(double) * (size_t)std::max(n_pl, 2) * nsys);
     double *pd = part.as<double>();
@@ -1307,6 +1385,8 @@ static void run_chain_batched(chess_ctx *ctx, BatchChain &rq) {
         ep.prev = uprev;
         ep.nacc = rq.nq;
         ep.row_sys = rq.d_row_sys;
+        ep.sys_last = rq.sys_npl ? dlast.as<int32_t>() : nullptr;
+        ep.step = k;
         for (int q = 0; q < rq.nq; ++q) {
             ep.acc[q] = rq.acc[q];
             ep.coef_sys[q] = dcoef.as<double>() + ((size_t)q * n_pl + k + 1) * nsys;
@@ -1830,7 +1910,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     int n_pl = 0, reexp = 0, passes = 0;
     double penalty = std::numeric_limits<double>::quiet_NaN();
     double ms_chain = 0.0, kernel_ms = 0.0, kernel_ms_acc = 0.0;
-    int variant = -1, variant_moments = -1;
+    int variant = -1, variant_moments = -1, tile_rows = 0;
     bool have_hist = false;
     Timer tm(st);
     // Width check of Sec. "Fermi Operator Expansion" (adapt_kt): the chain
@@ -1890,6 +1970,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         if (rq.nq > 0) kernel_ms_acc += rq.kernel_ms;
         else variant_moments = rq.variant;
         variant = rq.variant;
+        tile_rows = rq.tile_rows;
         passes++;
         const hostmath::BoundsCheck chk = hostmath::bounds_check(mom, n);
         penalty = chk.penalty;
@@ -2022,6 +2103,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         info->ms_chain_kernel = kernel_ms;
         info->ms_chain_kernel_acc = kernel_ms_acc;
         info->kernel_variant_moments = variant_moments;
+        info->tile_rows = tile_rows;
         info->kernel_variant = variant;
         info->pred_lo = pred[0];
         info->pred_hi = pred[1];
@@ -2346,6 +2428,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
     sc.acc[1] = accSinv.as<double>();
     sc.row0 = &row0;
     sc.d_row_sys = d_row_sys.as<int32_t>();
+    sc.sys_npl = &npls;
     sc.use_graph = use_graph;
     sc.moments = &smom;
     run_chain_batched(ctx, sc);
@@ -2446,6 +2529,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
     for (int q = 0; q < 3; ++q) hc.acc[q] = accK[q].as<double>();
     hc.row0 = &row0;
     hc.d_row_sys = d_row_sys.as<int32_t>();
+    hc.sys_npl = &npl;
     hc.use_graph = use_graph;
     hc.moments = &hmom;
     run_chain_batched(ctx, hc);

@@ -56,7 +56,20 @@ struct Epilogue {
     // (tiles never straddle systems) instead of coef[q]
     const int32_t *row_sys = nullptr;
     const double *coef_sys[4] = {nullptr, nullptr, nullptr, nullptr};
+    // batches: the last chain step each system needs (sys_last[s]) and the
+    // step of this launch; the tiles of a system past its last step return
+    // at once (their T, sums and moments are no longer read)
+    const int32_t *sys_last = nullptr;
+    int step = 0;
 };
+
+// True when this tile's system needs no more chain steps (see Epilogue); the
+// caller returns, after its trace partial is set to 0.
+__device__ inline bool tile_finished(const Epilogue &ep, int tile, int row0) {
+    if (!ep.sys_last || !ep.row_sys || ep.step <= ep.sys_last[ep.row_sys[row0]]) return false;
+    if (threadIdx.x == 0 && ep.trace_partial) ep.trace_partial[tile] = 0.0;
+    return true;
+}
 
 struct ProductOperands {
     const int64_t *a_rp;

@@ -227,6 +227,7 @@ __global__ __launch_bounds__(64 * NW) void k_product(ProductPlanDev plan, Produc
     if (tile >= ntiles) return;
     const LdsLayout L = lds_layout<T, B, CMAX, NW, PREF>(plan);
     const int row0 = plan.tile_row0[tile];
+    if (tile_finished(ep, tile, row0)) return;
     const int c = plan.tile_row0[tile + 1] - row0;
     stage_tile<T, B, CMAX, NT>(plan, ops, smem, L, tile, row0, c);
     // weights of the float64 sums: in batches (row_sys set; tiles never

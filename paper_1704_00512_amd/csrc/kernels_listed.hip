@@ -150,6 +150,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed(ListedPlanDev plan, ProductO
     if (tile >= ntiles) return;
     const ListedLds L = listed_lds<T, B, NW, EW, BD>(plan);
     const int row0 = plan.tile_row0[tile];
+    if (tile_finished(ep, tile, row0)) return;
     const int c = plan.tile_row0[tile + 1] - row0;
     const int64_t ab0 = ops.a_rp[row0];
 
@@ -701,6 +702,7 @@ __global__ __launch_bounds__(64 * NW) void k_listed9(ListedPlanDev plan, Product
     if (tile >= ntiles) return;
     const ListedLds L = listed_lds<float, 9, NW, EW, true>(plan);
     const int row0 = plan.tile_row0[tile];
+    if (tile_finished(ep, tile, row0)) return;
     const int c = plan.tile_row0[tile + 1] - row0;
     const int64_t ab0 = ops.a_rp[row0];
     float *As = reinterpret_cast<float *>(smem + L.a);
@@ -887,6 +889,7 @@ void k_lean(ListedPlanDev plan, ProductOperands ops, Epilogue ep) {
     if (tile >= ntiles) return;
     const LeanLds L = lean_lds<NW>(plan);
     const int row0 = plan.tile_row0[tile];
+    if (tile_finished(ep, tile, row0)) return;
     const int c = plan.tile_row0[tile + 1] - row0;
     const int64_t ab0 = ops.a_rp[row0];
     const int64_t j0 = plan.j_off[tile];
@@ -1213,6 +1216,7 @@ __global__ __launch_bounds__(64 * NW) void k_lean9(ListedPlanDev plan, ProductOp
     if (tile >= ntiles) return;
     const Lean9Lds L = lean9_lds<NW>(plan);
     const int row0 = plan.tile_row0[tile];
+    if (tile_finished(ep, tile, row0)) return;
     const int c = plan.tile_row0[tile + 1] - row0;
     const int64_t ab0 = ops.a_rp[row0];
     const int64_t j0 = plan.j_off[tile];
@@ -1648,6 +1652,14 @@ hipError_t dispatch_listed(int dtype, int b, const ListedPlanDev &plan, const Pr
         if (dtype != 1 || b != 4 || d < 0 || d > 2) return hipErrorInvalidValue;
         return launch_stat_product(ops.opmode, d == 0 ? 8 : d == 1 ? 4 : 16, plan, ops, ep, st, lds_out);
     }
+    if (b == 4) {
+        // the output-stationary ids, for tiles of any height
+        const int d = plan.variant - (dtype == 1 ? kStatVariantF32 : kStatVariantF64);
+        if (d >= 0 && d <= 2) {
+            const int nw = dtype == 1 ? (d == 0 ? 8 : d == 1 ? 4 : 16) : (d == 0 ? 4 : d == 1 ? 8 : 16);
+            return launch_stat_product(dtype == 1 ? kStatF32 : kStatF64, nw, plan, ops, ep, st, lds_out);
+        }
+    }
     if (dtype == 0 && b == 4) return launch_lb<double, 4>(plan, ops, ep, st, lds_out);
     if (dtype == 0 && b == 9) return launch_lb<double, 9>(plan, ops, ep, st, lds_out);
     if (dtype == 1 && b == 4) return launch_lb<float, 4>(plan, ops, ep, st, lds_out);
@@ -1664,7 +1676,8 @@ hipError_t launch_listed_product(int dtype, int b, const ListedPlanDev &plan,
 
 int listed_product_variants(int dtype, int b, const ListedPlanDev &plan) {
     if (b == 9 && dtype == 1 && plan.cmax == 2) return 5;  // VALU, MFMA with 4 or 8 waves, pipelined MFMA
-    if (b != 4 || plan.cmax != 4) return 1;
+    if (b != 4) return 1;
+    // b = 4: every id (other tile heights than 4 take the output-stationary ones)
     return dtype == 0 ? LVariant<double, 4, 4>::COUNT : LVariant<float, 4, 4>::COUNT;
 }
 
@@ -1673,8 +1686,11 @@ bool listed_product_variant_ok(int dtype, int b, const ListedPlanDev &plan, int 
     if (opmode != 0) return dtype == 1 && stat_ok && v >= kStatVariantF32 && v <= kStatVariantF32 + 2;
     if (b == 9 && dtype == 1 && plan.cmax == 2)
         return v >= 0 && v < 5 && (v < 3 || (plan.off31 && plan.entry_width == 1));
-    if (b != 4 || plan.cmax != 4) return v == 0;
     const int v0 = dtype == 0 ? kStatVariantF64 : kStatVariantF32;
+    // b = 4 tiles of other heights (chosen by the tile tuner): the
+    // output-stationary kernel only, which takes any tile of 1..4 rows
+    if (b == 4 && plan.cmax != 4) return stat_ok && v >= v0 && v <= v0 + 2;
+    if (b != 4 || plan.cmax != 4) return v == 0;
     if (v >= v0) return v <= v0 + 2 && stat_ok;
     if (v >= 16 && !(dtype == 1 && plan.lean_rec && plan.entry_width == 1)) return false;
     return dtype == 0 ? LVariant<double, 4, 4>::ok(v) : LVariant<float, 4, 4>::ok(v);

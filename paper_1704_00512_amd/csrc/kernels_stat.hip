@@ -108,6 +108,7 @@ __global__ __launch_bounds__(64 * NW) void k_stat(ListedPlanDev plan, ProductOpe
     const int tile = (wg & 7) * (nt8 >> 3) + (wg >> 3);
     if (tile >= ntiles) return;
     const int row0 = plan.tile_row0[tile];
+    if (tile_finished(ep, tile, row0)) return;
     const int c = plan.tile_row0[tile + 1] - row0;
     const int64_t ab0 = ops.a_rp[row0];
     // cumulative row ends in source blocks (rows past c have length 0)

@@ -177,3 +177,21 @@ def test_batched_long_rows_use_the_searching_product(gpu_ctx, precision, tol):
             err = float(np.max(np.abs(r["K"][q].cpu().numpy() - Ko)))
             print(f"[batched] long rows {precision}: system n={s.n} K[{q}] err {err:.2e}", flush=True)
             assert err < tol, (s.n, q)
+
+
+def test_batched_two_row_tiles(gpu_ctx, monkeypatch):
+    # the tile tuner's 2-row plan in a batch: tiles still start at every
+    # system (the b = 4 systems of the batch), float32, against the oracle
+    monkeypatch.setenv("CHESS_TILE_ROWS", "2")
+    ss = [s for s in systems() if s.b == 4]
+    args = batch_args(ss)
+    res = chess_fermi_operator_batched(gpu_ctx, args, precision="f32", bounds_mode="lanczos")
+    for s, a, r in zip(ss, args, res):
+        inf = r["info"]
+        sb, hb = (inf["s_lo"], inf["s_hi"]), (inf["lo"], inf["hi"])
+        H, S, P = bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k)
+        for q in range(3):
+            Ko, _ = opl.fermi_operator(H, S, P, s.n_electrons, s.kT, s_bounds_=sb,
+                                       n_pl_s=inf["n_pl_s"], h_bounds=hb, n_pl=inf["n_pl"],
+                                       mu=a["mu_trial"][q])
+            assert np.max(np.abs(r["K"][q].cpu().numpy() - Ko)) < 1e-5, (s.n, q)

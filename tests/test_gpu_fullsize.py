@@ -149,3 +149,46 @@ def inverse_sqrt_check(gpu_ctx, name, precision, tol):
     print(f"[fullsize] {name} {precision} S^-1/2 (bounds [{lo:.4f}, {hi:.4f}], n_pl {n_pl}): "
           f"max |GPU - oracle| over 16 columns = {worst:.3e}", flush=True)
     assert worst < tol
+
+
+def test_prec9000_eigs_window_against_the_oracle_extraction(gpu_ctx):
+    """Eigenvalues in an interval (Sec. "Extraction of selected eigenvalues")
+    at 9 000 rows: with S = I the frame is the identity (X = c I, c = 1 to the
+    x^-1/2 fit's rounding), so the library's chain on H' is the chain on H,
+    whose columns the test above checks against the oracle.  The library's
+    eigenvalues must equal the oracle's extraction from those moments (the
+    moments of chess_chebyshev on H with the same bounds and degree)."""
+    from paper_1704_00512_amd import chess_eigs_in_interval
+    s = workload("prec9000")
+    dev = torch.device("cuda")
+    ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx, dev)
+    pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx, dev)
+    H = torch.tensor(s.H, device=dev)
+    # S = I on the pattern of H
+    eye = np.zeros_like(s.S)
+    dpos = g.positions_in_pattern(s.pat_h, np.arange(s.pat_h.nb), np.arange(s.pat_h.nb))
+    eye[dpos] = np.eye(s.b)
+    S = torch.tensor(eye, device=dev)
+    e0, e1 = g.extreme_eigenvalues(s.pat_h, s.H)
+    w = e1 - e0
+    lo, hi = e0 - 0.01 * w, e1 + 0.01 * w
+    n_pl, width = 1200, 3e-3
+    _, mom = chess_chebyshev(gpu_ctx, H, ph, lo, hi, pk, n_pl, precision="f64")
+    assert abs(mom[0] - s.n) < 1e-9 * s.n and np.all(np.abs(mom) <= 1.0001 * s.n)
+    # a window about the median of the spectrum (N(e) = n / 2)
+    mid, _ = cb.bisect_mu(mom, lo, hi, width, 0.5 * s.n, 1e-6 * s.n, "erfc", lo, hi)
+    e_lo, e_hi = mid - 0.006, mid + 0.006
+    print(f"[fullsize] prec9000 eigenvalues in [{e_lo:.4f}, {e_hi:.4f}], bounds [{lo:.4f}, {hi:.4f}]",
+          flush=True)
+    ev, info = chess_eigs_in_interval(gpu_ctx, H, ph, S, ph, e_lo, e_hi, pk, precision="f64",
+                                      eig_width=width, n_pl=n_pl, bounds=(lo, hi),
+                                      s_bounds=(0.5, 1.5), n_pl_s=40)
+    assert info["n_pl"] == n_pl and (info["lo"], info["hi"]) == (lo, hi)
+    print(f"[fullsize] prec9000 eigenvalues: {ev.shape[0]} from the library; oracle extraction",
+          flush=True)
+    ref = cb.eigenvalues_from_moments(mom, lo, hi, width, e_lo, e_hi)
+    print(f"[fullsize] prec9000 eigenvalues: oracle {ref.shape[0]}, max diff "
+          f"{np.max(np.abs(ev - ref)) if ev.shape == ref.shape and ev.size else float('nan'):.2e}",
+          flush=True)
+    assert ev.shape == ref.shape and ev.shape[0] >= 15
+    assert np.max(np.abs(ev - ref)) < 1e-8

@@ -372,3 +372,35 @@ def test_errors_are_reported(gpu_ctx):
         chess_eigs_in_interval(gpu_ctx, H, ph, S, ph, -1.1, -0.9, pk, capacity=2, precision="f64",
                                n_pl=200, s_bounds=(0.25, 2.05), n_pl_s=40, bounds=(-1.9, 0.1))
     assert e.value.name == "CHESS_E_CAPACITY"
+
+
+@pytest.mark.parametrize("rows", [1, 2])
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_chain_tile_heights(gpu_ctx, monkeypatch, rows, precision, tol):
+    # b = 4 plans with tiles of other heights than 4 (the tile tuner's
+    # alternatives; the output-stationary kernel), two sums, against the oracle
+    monkeypatch.setenv("CHESS_TILE_ROWS", str(rows))
+    s, accs, mom, acc_o, mom_o = chain_case(gpu_ctx, SYSL, 70, precision, nq=2)
+    assert np.max(np.abs(mom - mom_o)) < tol * s.n
+    for q in range(2):
+        ref = bm(s.pat_k).to_block(acc_o[q])
+        assert np.max(np.abs(accs[q].cpu().numpy() - ref)) < tol, (rows, precision, q)
+
+
+def test_fermi_operator_reports_its_tile_height(gpu_ctx, monkeypatch):
+    s = system(*SYS4)
+    common = dict(precision="f32", s_bounds=(0.25, 2.05), n_pl_s=40, bounds=(-1.9, 0.1), n_pl=120,
+                  mu=-0.95)
+    K4, i4 = chess_fermi_operator(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h),
+                                  gpat(s.pat_k), s.n_electrons, 0.02, **common)
+    assert i4["tile_rows"] in (2, 4)
+    monkeypatch.setenv("CHESS_TILE_ROWS", "2")
+    K2, i2 = chess_fermi_operator(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h),
+                                  gpat(s.pat_k), s.n_electrons, 0.02, **common)
+    assert i2["tile_rows"] == 2 and 24 <= i2["kernel_variant"] <= 26
+    assert np.max(np.abs(K2.cpu().numpy() - K4.cpu().numpy())) < 1e-5
+    monkeypatch.setenv("CHESS_TILE_ROWS", "3")  # no kernel is built for 3-row tiles
+    with pytest.raises(ChessError) as e:
+        chess_fermi_operator(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h),
+                             gpat(s.pat_k), s.n_electrons, 0.02, **common)
+    assert e.value.name == "CHESS_E_ARG"
