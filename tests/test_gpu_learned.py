@@ -125,7 +125,8 @@ def test_learned_predictor_gain_on_held_out_systems():
     blob = np.load(MODEL)
     ratios, bis_l, bis_g, fallbacks = [], [], [], 0
     for i in range(8):
-        s = g.predictor_system(g.PREDICTOR_TEST_SEED0 + 1000 + i)
+        # held-out seeds of the training distribution, at its small end
+        s = g.predictor_system(g.PREDICTOR_TEST_SEED0 + 1000 + i, n_min=500, n_max=1000)
         print(f"[learned] held-out seed {g.PREDICTOR_TEST_SEED0 + 1000 + i} n={s.n} kT={s.kT:.4f}",
               flush=True)
         ctx = Context(0)
@@ -160,7 +161,7 @@ def test_learned_lanczos_bounds_are_the_intersection(gpu_ctx):
     the result that of the Lanczos form."""
     chess_model_load(gpu_ctx, np.load(MODEL))
     for i in range(3):
-        s = g.predictor_system(g.PREDICTOR_TEST_SEED0 + 2000 + i)
+        s = g.predictor_system(g.PREDICTOR_TEST_SEED0 + 2000 + i, n_min=500, n_max=700)
         print(f"[learned] intersection, seed {g.PREDICTOR_TEST_SEED0 + 2000 + i} n={s.n}", flush=True)
         dv = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
         ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx)

@@ -325,7 +325,7 @@ CONFIGS = {
 PREDICTOR_TRAIN_SEED0, PREDICTOR_TEST_SEED0 = 40000, 50000
 
 
-def predictor_system(seed: int, n_min: int = 40, n_max: int = 300) -> System:
+def predictor_system(seed: int, n_min: int = 500, n_max: int = 3000) -> System:
     rng = np.random.default_rng(seed)
     n_atoms = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
     b = 4 if rng.uniform() < 0.5 else 9
