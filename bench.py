@@ -156,6 +156,41 @@ def precision_table():
     return out
 
 
+def small_time_to_solution(ctx, name="dense256"):
+    """A whole density-kernel call, oracle against library, on the small
+    workload the oracle finishes in seconds: float64 on both sides, tol_fit
+    1e-6, the library with its Lanczos bounds and the oracle given the bounds
+    the library ended with (so both run the same expansion), each from the
+    matrices to K."""
+    import numpy as np
+    import torch
+    from oracle import pipeline as opl
+    from paper_1704_00512_amd import BlockPattern, chess_fermi_operator
+    from workloads.generator import make_config
+    s = make_config(name)
+    dev = torch.device("cuda:0")
+    ph = BlockPattern.from_host(s.b, s.pat_h.row_ptr, s.pat_h.col_idx, dev)
+    pk = BlockPattern.from_host(s.b, s.pat_k.row_ptr, s.pat_k.col_idx, dev)
+    H, S = torch.tensor(s.H, device=dev), torch.tensor(s.S, device=dev)
+    run = lambda: chess_fermi_operator(ctx, H, ph, S, ph, pk, s.n_electrons, s.kT, precision="f64",
+                                       bounds_mode="lanczos", tol_fit=1e-6, tol_fit_s=1e-7)
+    run()  # plans and variant timing
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    K, gi = run()
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    bm = lambda p, v=None: opl.BlockMat(p.nb, p.b, p.row_ptr, p.col_idx, v)
+    t0 = time.perf_counter()
+    Ko, oi = opl.fermi_operator(bm(s.pat_h, s.H), bm(s.pat_h, s.S), bm(s.pat_k), s.n_electrons, s.kT,
+                                s_bounds_=(gi["s_lo"], gi["s_hi"]), h_bounds=(gi["lo"], gi["hi"]),
+                                tol_fit=1e-6, tol_fit_s=1e-7)
+    t_oracle = time.perf_counter() - t0
+    return dict(workload=f"{name}: {s.n} rows", oracle_ms=round(t_oracle * 1e3, 1),
+                library_f64_ms=round(t_gpu * 1e3, 1), n_pl=gi["n_pl"], oracle_n_pl=oi["n_pl"],
+                max_abs_diff=float(np.max(np.abs(K.cpu().numpy() - Ko))))
+
+
 def cpu_baseline(sysm, budget_s=20.0):
     """The oracle's float64 chain (one accumulator) on the host cores, timed on
     a bounded number of Chebyshev steps of the same matrices."""
@@ -298,6 +333,8 @@ def main():
                     help="only run one N_PL-term chain (one accumulator) on the workload's H, "
                          "for counter collection")
     ap.add_argument("--precision", default="f32", help="--chain-only: f32, f64, bf16 or bf16x3")
+    ap.add_argument("--chain-sums", type=int, default=1,
+                    help="--chain-only: float64 sums of the chain (0: a moments-only pass)")
     ap.add_argument("--form", default="learned_lanczos",
                     choices=("learned_lanczos", "learned", "lanczos", "gershgorin"),
                     help="bounds of the timed float32 form (learned*: the loaded predictor)")
@@ -336,8 +373,9 @@ def main():
         ctx = Context(0)
         n = args.chain_only
         t0 = time.perf_counter()
-        _, mom = chess_chebyshev(ctx, torch.tensor(sysm.H, device=dev), ph, -3.0, 0.5, pk, n,
-                                 np.ones((1, n)) * 1e-3, precision=args.precision)
+        coef = np.ones((args.chain_sums, n)) * 1e-3 if args.chain_sums > 0 else None
+        _, mom = chess_chebyshev(ctx, torch.tensor(sysm.H, device=dev), ph, -3.0, 0.5, pk, n, coef,
+                                 precision=args.precision)
         torch.cuda.synchronize()
         log(f"chain of {n} terms ({args.precision}, variant {args.variant}): "
             f"{(time.perf_counter() - t0) * 1e3:.0f} ms, t_1 = {mom[1]:.6f}")
@@ -519,6 +557,7 @@ def main():
     # the other single-precision forms (Lanczos, the predictor alone), untimed
     out["config"]["bisect_iters"] = info["bisect_iters"]
     out["config"]["bounds"] = [info["lo"], info["hi"]]
+    out["config"]["tile_rows"] = info["tile_rows"]
     if form.startswith("learned"):
         out["config"]["fallback"] = info["fallback"]
         out["config"]["pred"] = [info["pred_lo"], info["pred_hi"], info["pred_mu"]]
@@ -653,6 +692,7 @@ def main():
         nsteps = max(n_pl - 2, 0) * passes + max(info["n_pl_s"] - 2, 0)
         cb["chain_time_to_solution_estimate_ms"] = round(cb["ms_per_step"] * nsteps, 1)
         cb["chain_steps_of_the_call"] = nsteps
+        cb["time_to_solution_small"] = small_time_to_solution(ctx)
         out["cpu_baseline"] = cb
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -243,12 +243,17 @@ def summarise(rows):
         a = lambda key, rs=have: np.array([r[mode][key] for r in rs], dtype=np.float64)
         d = dict(systems=len(have), n_pl_mean=float(a("n_pl").mean()),
                  n_pl_median=float(np.median(a("n_pl"))), bisect_mean=float(a("bisect").mean()),
-                 passes_mean=float(a("passes").mean()), ms_mean=float(a("ms").mean()))
+                 passes_mean=float(a("passes").mean()), ms_mean=float(a("ms").mean()),
+                 ms_median=float(np.median(a("ms"))))
         if sub:
             g = lambda key: np.array([r["gershgorin"][key] for r in sub], dtype=np.float64)
             m = lambda key: np.array([r[mode][key] for r in sub], dtype=np.float64)
             d.update(terms_vs_gershgorin=float(m("n_pl").sum() / g("n_pl").sum()),
-                     time_vs_gershgorin=float(m("ms").sum() / g("ms").sum()))
+                     time_vs_gershgorin=float(m("ms").sum() / g("ms").sum()),
+                     time_vs_gershgorin_median=float(np.median(m("ms") / g("ms"))))
+        if mode != "lanczos":
+            lz = np.array([r["lanczos"]["ms"] for r in have])
+            d.update(time_vs_lanczos_median=float(np.median(a("ms") / lz)))
         if mode != "lanczos":
             d.update(max_abs_dK=float(a("max_abs_dK").max()), max_dmu=float(a("dmu").max()))
         if mode.startswith("learned"):
