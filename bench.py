@@ -8,8 +8,10 @@ Tr(KS), inputs resident in HBM.
 
 Printed JSON line:
   value        Chebyshev SpMM throughput in algorithmic GB/s: algorithmic
-               bytes of every chain-product launch in the timed steps divided
-               by their device time (HIP events on the library's stream);
+               bytes of every chain step in the timed steps (a product; in
+               the moments-only pass, which runs half the chain, a product
+               and the Frobenius dot pair of its output) divided by their
+               device time (HIP events on the library's stream);
   ms_per_step  density-kernel time to solution of the timed form (float32
                chain, tol_fit 1e-6, bounds checked by Eq. 6): by default the
                learned predictor's mu bracket and its interval intersected
@@ -450,10 +452,15 @@ def main():
     n_pl, passes = info["n_pl"], info["passes"]
     hist = passes == 1
     steps_per_pass = max(n_pl - 2, 0)
-    b1 = chain_step_cost(sysm, 4, 0, hist)
+    # the moments-only pass runs half its chain: each of its steps is one
+    # product and one Frobenius dot pair (reading T_{m+1} and T_m once more)
+    m_steps = info["moment_products"] if not hist else 0
+    a_steps = steps_per_pass
+    nk_vals = sysm.pat_k.nnzb * sysm.b * sysm.b
+    b1 = chain_step_cost(sysm, 4, 0, hist) + (0 if hist else 2 * 4 * nk_vals)
     b2 = chain_step_cost(sysm, 4, 1, False)
-    bytes_call = steps_per_pass * b1 + (0 if hist else steps_per_pass * b2)
-    launches_call = steps_per_pass * passes
+    bytes_call = (a_steps * b1) if hist else (m_steps * b1 + a_steps * b2)
+    launches_call = a_steps if hist else m_steps + a_steps
     log("counting block triples for the flop count")
     triples = count_triples(sysm)
     flops_launch = 2.0 * sysm.b ** 3 * triples
@@ -468,20 +475,20 @@ def main():
     # the accumulating pass, from the library's per-pass device times
     per_pass = []
     acc_ms = sum(i.get("ms_chain_kernel_acc", float("nan")) for i in infos) / len(infos)
-    if not hist and acc_ms == acc_ms and steps_per_pass > 0:
-        for name, byts, ms in (("moments", b1, kern_ms - acc_ms), ("accumulate", b2, acc_ms)):
-            ms_l = ms / steps_per_pass
+    if not hist and acc_ms == acc_ms and steps_per_pass > 0 and m_steps > 0:
+        for name, byts, ms, nst in (("moments", b1, kern_ms - acc_ms, m_steps), ("accumulate", b2, acc_ms, a_steps)):
+            ms_l = ms / nst
             th, ta = byts / (HBM_PEAK_GBS * 1e9), flops_launch / (FP32_PEAK_TFLOPS * 1e12)
             if th >= ta:
                 ach = byts / (ms_l * 1e-3) / 1e9
                 per_pass.append(dict(pass_=name, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS,
                                      unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), avg_launch_ms=round(ms_l, 4),
-                                     algorithmic_bytes=int(byts)))
+                                     algorithmic_bytes=int(byts), steps=nst))
             else:
                 ach = flops_launch / (ms_l * 1e-3) / 1e12
                 per_pass.append(dict(pass_=name, bound="mfma", achieved=round(ach, 2), peak=FP32_PEAK_TFLOPS,
                                      unit="TFLOP/s", frac=round(ach / FP32_PEAK_TFLOPS, 4),
-                                     avg_launch_ms=round(ms_l, 4), flops=flops_launch))
+                                     avg_launch_ms=round(ms_l, 4), flops=flops_launch, steps=nst))
     # the call as a whole: HBM when its bytes take longer than its flops
     if t_hbm >= t_alu:
         roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -655,15 +662,17 @@ def main():
         ctx.set_progress(None)
         K_plain = K.cpu().numpy()
         diff = float(np.max(np.abs(K_plain - K_fast)))
-        pl_steps = max(pinfo["n_pl"] - 2, 0) * pinfo["passes"]
+        pl_acc_steps = max(pinfo["n_pl"] - 2, 0)
+        pl_steps = pinfo["moment_products"] + pl_acc_steps * (pinfo["passes"] - (1 if pinfo["moment_products"] else 0))
         out["plain_f64"] = dict(ms=round(tp, 1), n_pl=pinfo["n_pl"], passes=pinfo["passes"],
                                 bounds=[pinfo["lo"], pinfo["hi"]], mu=pinfo["mu"],
                                 max_abs_diff_fast_vs_plain=diff,
                                 speedup_fast_vs_plain=round(tp / ms_per_step, 2),
-                                avg_launch_ms=round(pinfo["ms_chain_kernel"] / max(pl_steps, 1), 4),
+                                avg_launch_ms=round(pinfo["ms_chain_kernel_acc"] / max(pl_acc_steps, 1), 4),
+                                chain_products=pl_steps, moment_products=pinfo["moment_products"],
                                 terms_ratio=round(pinfo["n_pl"] * pinfo["passes"] / max(n_pl * passes, 1), 3))
-        # the float64 chain launch against its own roof (the accumulating
-        # pass is HBM-bound, the moments pass float64-MFMA-bound)
+        # the float64 product launch of the accumulating pass against its own
+        # roof (HBM-bound)
         b64 = chain_step_cost(sysm, 8, 1, False)
         t64 = max(b64 / (HBM_PEAK_GBS * 1e9), flops_launch / (FP64_PEAK_TFLOPS * 1e12))
         out["plain_f64"]["frac_of_roofline"] = round(t64 * 1e3 / out["plain_f64"]["avg_launch_ms"], 4)
@@ -673,13 +682,13 @@ def main():
         # step; with no room for the stored T_k at this size, each step is a
         # whole accumulating pass plus the post-transform (not run: about
         # 15 minutes here, so derived from the measured pass times)
-        pass_ms = pinfo["ms_h_chain"] / max(pinfo["passes"], 1)
+        pass_ms = pinfo["ms_chain_kernel_acc"]
         lit = tp - pinfo["ms_h_chain"] - pinfo["ms_post"] + pinfo["bisect_iters"] * (pass_ms + pinfo["ms_post"])
         out["plain_f64"]["paper_literal_estimate"] = dict(
             ms=round(lit, 1), bisect_iters=pinfo["bisect_iters"],
             speedup_fast_vs_paper_literal=round(lit / ms_per_step, 2),
             basis="not run: the plain form's time without its H-chain passes and post-transform, "
-                  "plus one H-chain pass (the measured average) and one post-transform per "
+                  "plus one accumulating H-chain pass (as measured) and one post-transform per "
                   "bisection step of the same search")
         log(f"plain f64: {tp:.0f} ms n_pl={pinfo['n_pl']} max|K_fast-K_plain|={diff:.2e}; "
             f"paper-literal estimate {lit:.0f} ms ({pinfo['bisect_iters']} steps)")
@@ -689,7 +698,7 @@ def main():
         # the oracle's time for the chain steps of the timed call (both passes
         # and the S chain), from its measured time per step; the sandwich
         # products and host work of the call are not included
-        nsteps = max(n_pl - 2, 0) * passes + max(info["n_pl_s"] - 2, 0)
+        nsteps = info["chain_steps"]
         cb["chain_time_to_solution_estimate_ms"] = round(cb["ms_per_step"] * nsteps, 1)
         cb["chain_steps_of_the_call"] = nsteps
         cb["time_to_solution_small"] = small_time_to_solution(ctx)

@@ -200,6 +200,10 @@ typedef struct {
      * CHESS_TILE_ROWS = 1, 2 or 4 in the environment; 0 for the searching
      * kernel) */
     int32_t tile_rows;
+    /* chess_fermi_operator: product launches of the moments-only passes; such
+     * a pass runs half its chain (n_pl / 2 - 1 products) and takes the other
+     * moments from Frobenius products of the T_m it computed */
+    int32_t moment_products;
 } chess_info;
 
 /*

@@ -67,7 +67,7 @@ class chess_info(ctypes.Structure):
                 ("kt_used", ctypes.c_double), ("kt_halvings", ctypes.c_int32),
                 ("homo", ctypes.c_double), ("lumo", ctypes.c_double),
                 ("ms_chain_kernel_acc", ctypes.c_double), ("kernel_variant_moments", ctypes.c_int32),
-                ("tile_rows", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("moment_products", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

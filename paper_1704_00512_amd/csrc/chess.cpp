@@ -1026,6 +1026,7 @@ struct ChainRequest {
     double kernel_ms = 0.0;  // out: device time of the product launches
     int variant = -1;        // out: kernel variant of the listed product (-1: searching kernel)
     int tile_rows = 0;       // out: rows per tile of the listed product's plan
+    int products = 0;        // out: product launches of the chain
 };
 
 // Kernel variant of a listed plan.  CHESS_LISTED_VARIANT=<v> in the
@@ -1157,6 +1158,9 @@ static ListedPlan *tune_tile_rows(chess_ctx *ctx, ListedPlan *lp, int dtype, int
         if (!stat_ready(alt)) CHESS_THROW(CHESS_E_UNSUPPORTED, "CHESS_TILE_ROWS=%d: no output-stationary plan", rows);
         return pick(alt);
     }
+    // a variant forced by CHESS_LISTED_VARIANT names a kernel of the default
+    // plan (4-row tiles)
+    if (std::getenv("CHESS_LISTED_VARIANT")) return pick(lp);
     const int pass = nacc > 0 ? 1 : 0;
     for (const auto &tc : ctx->tile_choices)
         if (tc.a == A && tc.bt == Bt && tc.dtype == dtype && tc.breaks == lp->breaks && tc.opmode == opmode &&
@@ -1224,7 +1228,23 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     }
     const int ntiles = lplan->usable ? lplan->dev.ntiles : plan->dev.ntiles;
     const int nsteps = std::max(rq.n_pl, 2);
+    // Moments-only chains (no sums, no history) run to T_K, K = ceil((n_pl -
+    // 1) / 2), and take the rest of the moments from the product rule of
+    // Chebyshev polynomials, 2 T_m T_n = T_{m+n} + T_{|m-n|}: t_{2m} =
+    // 2 <T_m, T_m> - n and t_{2m+1} = 2 <T_{m+1}, T_m> - t_1, with <., .> the
+    // Frobenius product of the stored blocks.  This holds for the truncated
+    // chain too: column j of the truncated T_m is T_m(M_j) e_j with M_j the
+    // symmetric compression of M~ to that column's support (the columns obey
+    // the recursion independently), so e_j^T T_{2m}(M_j) e_j = 2 |T_m e_j|^2 - 1.
+    const bool halve = rq.nq == 0 && !rq.hist && rq.moments && rq.n_pl > 4 && !std::getenv("CHESS_FULL_MOMENTS");
+    const int last = halve ? rq.n_pl / 2 : rq.n_pl - 1;  // highest T_m computed (ceil((n_pl - 1) / 2))
+    const int dparts = 256;
     DevBuf part(sizeof(double) * (size_t)nsteps * std::max(ntiles, 256));
+    DevBuf dpart, dred;
+    if (halve) {
+        dpart.alloc(sizeof(double) * 2 * (size_t)dparts * last);
+        dred.alloc(sizeof(double) * 2 * (size_t)last);
+    }
     DevBuf mom(sizeof(double) * nsteps);
     double *pd = part.as<double>();
     const int tparts = 256;
@@ -1235,10 +1255,16 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
         HIPCHECK(launch_trace(dtype, b, PK->nb, PK->d_diag.as<int64_t>(), U1.p, pd + tparts, tparts, st));
         HIPCHECK(launch_reduce_rows(1, tparts, pd + tparts, mom.as<double>() + 1, st));
     }
+    // <T_m, T_m> and <T_m, T_{m-1}> go to block m - 1 of the halving partials
+    auto dots = [&](int m, const void *tm, const void *tm1) {
+        HIPCHECK(launch_dot_pair(dtype, nK, tm, tm1, dpart.as<double>() + 2 * (size_t)dparts * (m - 1), dparts, st));
+    };
     void *ucur = U1.p, *uprev = U0.p;
     Timer tm(st);
     tm.start();
-    for (int k = 1; k + 1 < rq.n_pl; ++k) {
+    if (halve) dots(1, U1.p, U0.p);
+    rq.products = 0;
+    for (int k = 1; k + 1 <= last; ++k) {
         Epilogue ep;
         ep.alpha = 2.0;
         ep.beta = -1.0;
@@ -1249,18 +1275,36 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
             ep.coef[q] = rq.coef[(size_t)q * rq.n_pl + k + 1];
         }
         ep.hist = rq.hist ? (char *)rq.hist + (size_t)(k + 1) * tb : nullptr;
-        ep.trace_partial = pd + (size_t)(k + 1) * ntiles;
+        ep.trace_partial = halve ? nullptr : pd + (size_t)(k + 1) * ntiles;
         if (lplan->usable)
             product_listed(ctx, dtype, lplan, ucur, Bt.p, uprev, ep, rq.opmode, Bhi.p, Blo.p);
         else
             product(ctx, dtype, plan, ucur, Bt.p, uprev, ep);
+        rq.products++;
         std::swap(ucur, uprev);
+        if (halve) dots(k + 1, ucur, uprev);
         if (ctx->progress && (k + 1) % ctx->progress_every == 0) {
             HIPCHECK(hipStreamSynchronize(st));
-            ctx->progress(ctx->progress_user, rq.label, k + 1, rq.n_pl);
+            ctx->progress(ctx->progress_user, rq.label, halve ? 2 * (k + 1) : k + 1, rq.n_pl);
         }
     }
     rq.kernel_ms = tm.stop();
+    if (halve) {
+        HIPCHECK(launch_reduce_rows(2 * last, dparts, dpart.as<double>(), dred.as<double>(), st));
+        std::vector<double> red(2 * (size_t)last);
+        HIPCHECK(hipMemcpyAsync(red.data(), dred.p, sizeof(double) * red.size(), hipMemcpyDeviceToHost, st));
+        rq.moments->assign(rq.n_pl, 0.0);
+        HIPCHECK(hipMemcpyAsync(rq.moments->data(), mom.p, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        std::vector<double> &t = *rq.moments;
+        const double n = (double)PK->n();
+        // red[2 (m - 1)] = <T_m, T_m>, red[2 (m - 1) + 1] = <T_m, T_{m-1}>
+        for (int j = 2; j < rq.n_pl; ++j) {
+            const int m = j / 2;
+            t[j] = (j % 2 == 0) ? 2.0 * red[2 * (size_t)(m - 1)] - n : 2.0 * red[2 * (size_t)m + 1] - t[1];
+        }
+        return;
+    }
     if (rq.n_pl > 2)
         HIPCHECK(launch_reduce_rows(rq.n_pl - 2, ntiles, pd + 2 * (size_t)ntiles, mom.as<double>() + 2, st));
     if (rq.moments) {
@@ -1910,7 +1954,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
     int n_pl = 0, reexp = 0, passes = 0;
     double penalty = std::numeric_limits<double>::quiet_NaN();
     double ms_chain = 0.0, kernel_ms = 0.0, kernel_ms_acc = 0.0;
-    int variant = -1, variant_moments = -1, tile_rows = 0;
+    int variant = -1, variant_moments = -1, tile_rows = 0, moment_products = 0, products = 0;
     bool have_hist = false;
     Timer tm(st);
     // Width check of Sec. "Fermi Operator Expansion" (adapt_kt): the chain
@@ -1969,6 +2013,8 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         kernel_ms += rq.kernel_ms;
         if (rq.nq > 0) kernel_ms_acc += rq.kernel_ms;
         else variant_moments = rq.variant;
+        if (rq.nq == 0) moment_products += rq.products;
+        products += rq.products;
         variant = rq.variant;
         tile_rows = rq.tile_rows;
         passes++;
@@ -2068,6 +2114,7 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
             run_chain(ctx, rq);
             kernel_ms += rq.kernel_ms;
             kernel_ms_acc += rq.kernel_ms;
+            products += rq.products;
             variant = rq.variant;
             passes++;
         }
@@ -2092,7 +2139,8 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         info->passes = passes;
         info->bisect_iters = iters;
         info->reexpansions = reexp + F.s.reexp;
-        info->chain_steps = passes * std::max(n_pl - 2, 0) + std::max(F.s.n_pl - 2, 0);
+        info->chain_steps = products + std::max(F.s.n_pl - 2, 0);
+        info->moment_products = moment_products;
         info->ms_total = t_end - t_begin;
         info->ms_setup = t_setup - t_begin;
         info->ms_s_chain = F.ms_s;

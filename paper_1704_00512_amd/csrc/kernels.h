@@ -249,6 +249,10 @@ hipError_t launch_recombine(int dtype, int64_t n, int nk, const void *hist, cons
 // Per block row diagonal trace partials, reduced per tile of rows.
 hipError_t launch_trace(int dtype, int b, int nb, const int64_t *diag_idx, const void *val,
                         double *out_partial, int nparts, hipStream_t st);
+// Partials of the Frobenius products <x, x> (part[0 .. nparts)) and <x, y>
+// (part[nparts .. 2 nparts)) of two value arrays of n entries, 16-byte aligned.
+hipError_t launch_dot_pair(int dtype, int64_t n, const void *x, const void *y, double *part,
+                           int nparts, hipStream_t st);
 // out[s] = sum_t part[s * nparts + t], fixed order.
 hipError_t launch_reduce_rows(int nrows, int nparts, const double *part, double *out,
                               hipStream_t st);

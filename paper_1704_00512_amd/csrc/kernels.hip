@@ -714,6 +714,42 @@ __global__ void k_trace(int b, int nb, const int64_t *diag_idx, const T *val, do
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Per-workgroup partials of sum x^2 (part[w]) and sum x y (part[nparts + w])
+// over n values, accumulated in float64; 16-byte loads (n is a multiple of
+// 16 / sizeof(T): whole 4 x 4 or 9 x 9 block arrays of at least 16 values
+// are not, so a scalar tail takes the rest).
+template <typename T>
+__global__ void k_dot_pair(int64_t n, const T *x, const T *y, double *part) {
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
+    constexpr int W = 16 / sizeof(T);
+    const int nparts = gridDim.x;
+    const int64_t nv = n / W;
+    const V *xv = reinterpret_cast<const V *>(x);
+    const V *yv = reinterpret_cast<const V *>(y);
+    double sq = 0.0, xy = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += stride) {
+        const V a = xv[i], c = yv[i];
+        if constexpr (W == 4) {
+            sq += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z + (double)a.w * a.w;
+            xy += (double)a.x * c.x + (double)a.y * c.y + (double)a.z * c.z + (double)a.w * c.w;
+        } else {
+            sq += a.x * a.x + a.y * a.y;
+            xy += a.x * c.x + a.y * c.y;
+        }
+    }
+    for (int64_t i = nv * W + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        sq += (double)x[i] * x[i];
+        xy += (double)x[i] * y[i];
+    }
+    sq = block_sum(sq);
+    xy = block_sum(xy);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = sq;
+        part[nparts + blockIdx.x] = xy;
+    }
+}
+
 __global__ void k_reduce_rows(int nparts, const double *part, double *out) {
     double s = 0.0;
     const double *p = part + (int64_t)blockIdx.x * nparts;
@@ -980,6 +1016,17 @@ hipError_t launch_trace(int dtype, int b, int nb, const int64_t *diag_idx, const
     else
         hipLaunchKernelGGL(k_trace<float>, dim3(nparts), dim3(kWG), 0, st, b, nb, diag_idx,
                            (const float *)val, out_partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_pair(int dtype, int64_t n, const void *x, const void *y, double *part,
+                           int nparts, hipStream_t st) {
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_dot_pair<double>, dim3(nparts), dim3(kWG), 0, st, n, (const double *)x,
+                           (const double *)y, part);
+    else
+        hipLaunchKernelGGL(k_dot_pair<float>, dim3(nparts), dim3(kWG), 0, st, n, (const float *)x,
+                           (const float *)y, part);
     return hipGetLastError();
 }
 

@@ -404,3 +404,26 @@ def test_fermi_operator_reports_its_tile_height(gpu_ctx, monkeypatch):
         chess_fermi_operator(gpu_ctx, dt(s.H), gpat(s.pat_h), dt(s.S), gpat(s.pat_h),
                              gpat(s.pat_k), s.n_electrons, 0.02, **common)
     assert e.value.name == "CHESS_E_ARG"
+
+
+@pytest.mark.parametrize("spec", ["SYS4", "SYS9"])
+@pytest.mark.parametrize("n_pl", [5, 61, 70])
+@pytest.mark.parametrize("precision,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_moments_only_chain_runs_half(gpu_ctx, monkeypatch, spec, n_pl, precision, tol):
+    # a moments-only chain computes T_m up to m = n_pl / 2 and the other
+    # moments from <T_m, T_m> and <T_{m+1}, T_m> (product rule of Chebyshev
+    # polynomials, exact for the truncated chain); against the oracle's
+    # directly computed moments and against the library's full chain
+    sp = {"SYS4": SYS4, "SYS9": SYS9}[spec]
+    s = system(*sp)
+    e0, e1 = g.extreme_eigenvalues(s.pat_h, s.H)
+    lo, hi = e0 - 0.02 * (e1 - e0), e1 + 0.02 * (e1 - e0)
+    _, mom = chess_chebyshev(gpu_ctx, dt(s.H), gpat(s.pat_h), lo, hi, gpat(s.pat_k), n_pl,
+                             precision=precision)
+    Mt = opl.scaled(bm(s.pat_h, s.H).csr(), lo, hi)
+    _, mom_o = ocsr.chebyshev(Mt, bm(s.pat_k).pattern_csr(), n_pl, None)
+    assert np.max(np.abs(mom - mom_o)) < tol * s.n, (spec, n_pl, precision)
+    monkeypatch.setenv("CHESS_FULL_MOMENTS", "1")
+    _, mom_f = chess_chebyshev(gpu_ctx, dt(s.H), gpat(s.pat_h), lo, hi, gpat(s.pat_k), n_pl,
+                               precision=precision)
+    assert np.max(np.abs(mom - mom_f)) < tol * s.n
