@@ -453,11 +453,14 @@ def main():
     hist = passes == 1
     steps_per_pass = max(n_pl - 2, 0)
     # the moments-only pass runs half its chain: each of its steps is one
-    # product and one Frobenius dot pair (reading T_{m+1} and T_m once more)
+    # product and the Frobenius products of its output with T_m, fused in the
+    # output-stationary kernel's epilogue (reading T_m once more) or taken by
+    # k_dot_pair (reading T_{m+1} and T_m once more)
     m_steps = info["moment_products"] if not hist else 0
     a_steps = steps_per_pass
     nk_vals = sysm.pat_k.nnzb * sysm.b * sysm.b
-    b1 = chain_step_cost(sysm, 4, 0, hist) + (0 if hist else 2 * 4 * nk_vals)
+    fused_dots = 24 <= info["kernel_variant_moments"] <= 26
+    b1 = chain_step_cost(sysm, 4, 0, hist) + (0 if hist else (1 if fused_dots else 2) * 4 * nk_vals)
     b2 = chain_step_cost(sysm, 4, 1, False)
     bytes_call = (a_steps * b1) if hist else (m_steps * b1 + a_steps * b2)
     launches_call = a_steps if hist else m_steps + a_steps

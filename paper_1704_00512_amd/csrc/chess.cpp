@@ -1238,12 +1238,23 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     // the recursion independently), so e_j^T T_{2m}(M_j) e_j = 2 |T_m e_j|^2 - 1.
     const bool halve = rq.nq == 0 && !rq.hist && rq.moments && rq.n_pl > 4 && !std::getenv("CHESS_FULL_MOMENTS");
     const int last = halve ? rq.n_pl / 2 : rq.n_pl - 1;  // highest T_m computed (ceil((n_pl - 1) / 2))
-    const int dparts = 256;
+    // dot-pair workgroups: enough to stream the T_m arrays at full rate
+    const int dparts = (int)std::min<int64_t>(2048, std::max<int64_t>(64, nK / 4096));
     DevBuf part(sizeof(double) * (size_t)nsteps * std::max(ntiles, 256));
-    DevBuf dpart, dred;
+    // the output-stationary kernel adds the Frobenius products of its output
+    // per tile (Epilogue::sq_partial); the other kernels leave them to
+    // k_dot_pair after each product
+    const int v0s = dtype == 1 ? kStatVariantF32 : kStatVariantF64;
+    const bool fused = halve && lplan->usable &&
+                       (rq.opmode != 0 || (b == 4 && lplan->dev.variant >= v0s && lplan->dev.variant <= v0s + 2));
+    DevBuf dpart, dred, fpart, fred;
     if (halve) {
-        dpart.alloc(sizeof(double) * 2 * (size_t)dparts * last);
+        dpart.alloc(sizeof(double) * 2 * (size_t)dparts * (fused ? 1 : last));
         dred.alloc(sizeof(double) * 2 * (size_t)last);
+        if (fused) {
+            fpart.alloc(sizeof(double) * 2 * (size_t)ntiles * last);
+            fred.alloc(sizeof(double) * 2 * (size_t)last);
+        }
     }
     DevBuf mom(sizeof(double) * nsteps);
     double *pd = part.as<double>();
@@ -1276,13 +1287,18 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
         }
         ep.hist = rq.hist ? (char *)rq.hist + (size_t)(k + 1) * tb : nullptr;
         ep.trace_partial = halve ? nullptr : pd + (size_t)(k + 1) * ntiles;
+        if (fused) {
+            // rows m - 1 of the <T_m, T_m> and <T_m, T_{m-1}> partials, m = k + 1
+            ep.sq_partial = fpart.as<double>() + (size_t)k * ntiles;
+            ep.xy_partial = fpart.as<double>() + (size_t)(last + k) * ntiles;
+        }
         if (lplan->usable)
             product_listed(ctx, dtype, lplan, ucur, Bt.p, uprev, ep, rq.opmode, Bhi.p, Blo.p);
         else
             product(ctx, dtype, plan, ucur, Bt.p, uprev, ep);
         rq.products++;
         std::swap(ucur, uprev);
-        if (halve) dots(k + 1, ucur, uprev);
+        if (halve && !fused) dots(k + 1, ucur, uprev);
         if (ctx->progress && (k + 1) % ctx->progress_every == 0) {
             HIPCHECK(hipStreamSynchronize(st));
             ctx->progress(ctx->progress_user, rq.label, halve ? 2 * (k + 1) : k + 1, rq.n_pl);
@@ -1290,9 +1306,20 @@ static void run_chain(chess_ctx *ctx, ChainRequest &rq) {
     }
     rq.kernel_ms = tm.stop();
     if (halve) {
-        HIPCHECK(launch_reduce_rows(2 * last, dparts, dpart.as<double>(), dred.as<double>(), st));
+        HIPCHECK(launch_reduce_rows(fused ? 2 : 2 * last, dparts, dpart.as<double>(), dred.as<double>(), st));
         std::vector<double> red(2 * (size_t)last);
-        HIPCHECK(hipMemcpyAsync(red.data(), dred.p, sizeof(double) * red.size(), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipMemcpyAsync(red.data(), dred.p, sizeof(double) * (fused ? 2 : red.size()), hipMemcpyDeviceToHost, st));
+        if (fused && last > 1) {
+            // rows m = 2 .. last of the per-tile partials
+            HIPCHECK(launch_reduce_rows(2 * last, ntiles, fpart.as<double>(), fred.as<double>(), st));
+            std::vector<double> f(2 * (size_t)last);
+            HIPCHECK(hipMemcpyAsync(f.data(), fred.p, sizeof(double) * f.size(), hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            for (int m = 2; m <= last; ++m) {
+                red[2 * (size_t)(m - 1)] = f[(size_t)(m - 1)];
+                red[2 * (size_t)(m - 1) + 1] = f[(size_t)(last + m - 1)];
+            }
+        }
         rq.moments->assign(rq.n_pl, 0.0);
         HIPCHECK(hipMemcpyAsync(rq.moments->data(), mom.p, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));

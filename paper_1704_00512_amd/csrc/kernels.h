@@ -61,6 +61,11 @@ struct Epilogue {
     // at once (their T, sums and moments are no longer read)
     const int32_t *sys_last = nullptr;
     int step = 0;
+    // moments-only chains (output-stationary kernel only): per tile, the
+    // Frobenius products <Y', Y'> and <Y', A> of the finished output Y' with
+    // A (the chain's T_m, stored on the output's pattern), float64
+    double *sq_partial = nullptr;
+    double *xy_partial = nullptr;
 };
 
 // True when this tile's system needs no more chain steps (see Epilogue); the

@@ -181,12 +181,14 @@ __global__ __launch_bounds__(64 * NW) void k_stat(ListedPlanDev plan, ProductOpe
     const __amdgpu_buffer_rsrc_t r_prev = mkrsrc(ep.prev ? ep.prev : ops.a_val);
     const __amdgpu_buffer_rsrc_t r_out = mkrsrc(ops.c_out);
     const __amdgpu_buffer_rsrc_t r_hist = mkrsrc(ep.hist ? ep.hist : ops.c_out);
+    const __amdgpu_buffer_rsrc_t r_a = mkrsrc(ops.a_val);  // T_m in storage precision
+    const bool dots = ep.sq_partial != nullptr;
     __amdgpu_buffer_rsrc_t r_acc[NACC];
 #pragma unroll
     for (int qa = 0; qa < NACC; ++qa) r_acc[qa] = mkrsrc((qa < ep.nacc) ? ep.acc[qa] : ep.acc[0]);
     typedef __attribute__((address_space(3))) const unsigned char lds_u8;
     lds_u8 *As = (lds_u8 *)smem;
-    double tr = 0.0;
+    double tr = 0.0, dsq = 0.0, dxy = 0.0;
     const int g0 = plan.st_goff[tile], g1 = plan.st_goff[tile + 1];
     for (int g = g0 + wave; g < g1; g += NW) {
         const int li = plan.st_ginfo[2 * g];
@@ -318,6 +320,11 @@ __global__ __launch_bounds__(64 * NW) void k_stat(ListedPlanDev plan, ProductOpe
                                                               r_acc[qa], (int)(eoff * 8), 0, 0);
                 if (ep.hist) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, o), r_hist, (int)(eoff * 8), 0, 0);
                 if (((dmask >> slot) & 1u) && (lane >> 4) == (lane & 3)) tr += o;
+                if (dots) {
+                    const double a = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r_a, (int)(eoff * 8), 0, 0));
+                    dsq += o * o;
+                    dxy += o * a;
+                }
             } else {
                 f32x4 o;
 #pragma unroll
@@ -339,6 +346,14 @@ __global__ __launch_bounds__(64 * NW) void k_stat(ListedPlanDev plan, ProductOpe
                     }
                 }
                 if (ep.hist) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o), r_hist, (int)(eoff * 4), 0, 0);
+                if (dots) {
+                    const f32x4 a = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r_a, (int)(eoff * 4), 0, 0));
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        dsq += (double)o[v] * o[v];
+                        dxy += (double)o[v] * a[v];
+                    }
+                }
                 if ((dmask >> slot) & 1u) {
                     const int q = lane & 3;
                     const float d = q == 0 ? o[0] : q == 1 ? o[1] : q == 2 ? o[2] : o[3];
@@ -350,6 +365,14 @@ __global__ __launch_bounds__(64 * NW) void k_stat(ListedPlanDev plan, ProductOpe
     if (ep.trace_partial) {
         const double s = block_sum<NT>(tr);
         if (threadIdx.x == 0) ep.trace_partial[tile] = s;
+    }
+    if (dots) {
+        const double s1 = block_sum<NT>(dsq);
+        const double s2 = block_sum<NT>(dxy);
+        if (threadIdx.x == 0) {
+            ep.sq_partial[tile] = s1;
+            ep.xy_partial[tile] = s2;
+        }
     }
 }
 

@@ -427,3 +427,20 @@ def test_moments_only_chain_runs_half(gpu_ctx, monkeypatch, spec, n_pl, precisio
     _, mom_f = chess_chebyshev(gpu_ctx, dt(s.H), gpat(s.pat_h), lo, hi, gpat(s.pat_k), n_pl,
                                precision=precision)
     assert np.max(np.abs(mom - mom_f)) < tol * s.n
+
+
+@pytest.mark.parametrize("precision,variant,tol", [("f32", 24, TOL32), ("f32", 20, TOL32),
+                                                   ("f64", 12, TOL64), ("f64", 2, TOL64)])
+def test_moments_only_chain_fused_and_separate_dots(gpu_ctx, monkeypatch, precision, variant, tol):
+    # the output-stationary kernel adds the Frobenius products in its
+    # epilogue (24, 12); the other kernels leave them to k_dot_pair (20, 2)
+    monkeypatch.setenv("CHESS_LISTED_VARIANT", str(variant))
+    s = system(*SYSL)
+    e0, e1 = g.extreme_eigenvalues(s.pat_h, s.H)
+    lo, hi = e0 - 0.02 * (e1 - e0), e1 + 0.02 * (e1 - e0)
+    for n_pl in (64, 71):
+        _, mom = chess_chebyshev(gpu_ctx, dt(s.H), gpat(s.pat_h), lo, hi, gpat(s.pat_k), n_pl,
+                                 precision=precision)
+        Mt = opl.scaled(bm(s.pat_h, s.H).csr(), lo, hi)
+        _, mom_o = ocsr.chebyshev(Mt, bm(s.pat_k).pattern_csr(), n_pl, None)
+        assert np.max(np.abs(mom - mom_o)) < tol * s.n, (precision, variant, n_pl)
