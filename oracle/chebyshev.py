@@ -195,6 +195,17 @@ def penalty_valid(n_terms: int, n_rows: int, alpha: float = PENALTY_ALPHA) -> bo
     return fit_error(penalty_fn(alpha, -1.0, 1.0), -1.0, 1.0, m) * n_rows < 0.1
 
 
+def penalty_degree(n_rows: int, step: int = 8) -> int:
+    """Reading R7 for matrix powers: the fewest terms (a multiple of step, at
+    most 1024) with which Eq. 6 is trusted on n_rows rows (penalty_valid).
+    A power series shorter than this is checked on a moments-only chain of
+    this many terms before it is accumulated."""
+    m = step
+    while m < 1024 and not penalty_valid(m, n_rows):
+        m += step
+    return m
+
+
 def growth_ok(t: np.ndarray, n_rows: int) -> bool:
     """|T_k(x)| <= 1 on [-1, 1], so |Tr T_k| <= n whenever every eigenvalue of
     M~ is inside the bounds; reading R7 allows 1 %."""

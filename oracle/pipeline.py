@@ -93,12 +93,18 @@ def s_bounds(S: Csr, lanczos_k: int = 60, margin: float = 1e-3) -> tuple[float, 
     return lo, ghi
 
 
-def widen_power(lo: float, hi: float) -> tuple[float, float]:
-    """Reading R7 for matrix powers (growth test only): both sides move out by
-    10 % of the width, the lower bound at most halved so that it stays
-    positive for non-integer or negative exponents."""
+def widen_power(lo: float, hi: float, side: str = "both") -> tuple[float, float]:
+    """Reading R7 for matrix powers: the failing side moves out by 10 % of the
+    width ('both' after a failed growth test, whose side is not trusted when
+    the bounds may be off on both sides, e.g. a default guess), the lower
+    bound at most halved so that it stays positive for non-integer or
+    negative exponents."""
     w = hi - lo
-    return max(lo - 0.1 * w, 0.5 * lo), hi + 0.1 * w
+    if side in ("lo", "both"):
+        lo = max(lo - 0.1 * w, 0.5 * lo)
+    if side in ("hi", "both"):
+        hi = hi + 0.1 * w
+    return lo, hi
 
 
 def matrix_power(S: BlockMat, a: float, pattern: BlockMat, bounds=None, n_pl=None,
@@ -107,30 +113,46 @@ def matrix_power(S: BlockMat, a: float, pattern: BlockMat, bounds=None, n_pl=Non
     Returns (values [nnzb, b, b], info) (and extra powers from the same chain
     when `extra_powers` is given: a dict a' -> values).
 
-    Sec. "Determination of the eigenvalue bounds and polynomial degree": a
-    chain whose moments fail the growth test (an eigenvalue outside the
-    bounds) is redone with widened bounds (widen_power), at most
-    max_reexpand times; info['reexpansions'] counts them."""
+    Sec. "Determination of the eigenvalue bounds and polynomial degree": the
+    bounds are judged by the growth test and Eq. 6 (reading R7) on the
+    moments of at least penalty_degree(n) terms.  A shorter series is first
+    checked on a moments-only chain of that length; a longer one is checked
+    on its own moments.  A failure widens the bounds (widen_power: both sides
+    after the growth test, the penalty's side after Eq. 6) and redoes the
+    check, at most max_reexpand times; info['reexpansions'] counts the
+    widenings, info['penalty'] is Tr W^p for the final bounds and
+    info['check_terms'] the number of moments it was judged on."""
     Sc = S.csr()
     K = pattern.pattern_csr()
     lo, hi = bounds if bounds is not None else s_bounds(Sc)
     powers = (a,) + tuple(extra_powers)
     n_given = n_pl
+    n_check = cb.penalty_degree(K.n)
     reexp = 0
     while True:
         if n_given is None:
             n_pl = max(cb.degree(cb.power_fn(p), lo, hi, tol_fit) for p in powers)
-        coefs = np.stack([cb.cheb_coeffs(cb.power_fn(p), lo, hi, n_pl) for p in powers])
-        acc, mom = chebyshev(scaled(Sc, lo, hi), K, n_pl, coefs)
-        if cb.growth_ok(mom, K.n):
+        St = scaled(Sc, lo, hi)
+        if n_pl < n_check:
+            # too few terms for Eq. 6: judge the bounds on a moments-only
+            # chain of n_check terms before accumulating
+            _, mom_chk = chebyshev(St, K, n_check, None)
+            chk = cb.bounds_check(mom_chk, K.n)
+        if n_pl >= n_check or chk["ok"]:
+            coefs = np.stack([cb.cheb_coeffs(cb.power_fn(p), lo, hi, n_pl) for p in powers])
+            acc, mom = chebyshev(St, K, n_pl, coefs)
+            if n_pl >= n_check:
+                chk = cb.bounds_check(mom, K.n)
+        if chk["ok"]:
             break
         if reexp >= max_reexpand:
-            raise ValueError(f"bounds [{lo}, {hi}] still fail the growth test")
-        lo, hi = widen_power(lo, hi)
+            raise ValueError(f"bounds [{lo}, {hi}] still fail after {reexp} widenings")
+        lo, hi = widen_power(lo, hi, chk["side"] if chk["valid"] else "both")
         reexp += 1
     # left-multiplication chain -> values are those of p(S~) directly
     outs = [pattern.to_block(acc[q]) for q in range(len(powers))]
-    info = dict(lo=lo, hi=hi, n_pl=n_pl, moments=mom, reexpansions=reexp)
+    info = dict(lo=lo, hi=hi, n_pl=n_pl, moments=mom, reexpansions=reexp,
+                penalty=chk["penalty"], check_terms=max(n_pl, n_check))
     if extra_powers:
         return outs[0], info, {p: o for p, o in zip(extra_powers, outs[1:])}
     return outs[0], info

@@ -251,29 +251,111 @@ def test_widening_gives_the_matrix_function():
     assert abs(np.sum(cb.occ_erfc(ev, info["mu"], kT)) - n_e) < 1e-6
 
 
-def test_matrix_power_widens_on_growth():
-    # S with its smallest eigenvalue below the given lower bound: the growth
-    # test fails and both sides widen (the lower one at most halved) until the
-    # spectrum is inside; the result is then S^-1 on the dense pattern
-    lam = np.linspace(0.2, 1.6, 24)
-    rng = np.random.default_rng(5)
-    V, _ = np.linalg.qr(rng.standard_normal((24, 24)))
+def simulate_power_widening(lam, lo, hi, n_of, max_reexpand=3):
+    """Reading R7 for matrix powers driven by exact eigenvalues: the growth
+    test on max(n_pl, penalty_degree(n)) terms (a failure moves both sides),
+    then Eq. 6 from the eigenvalues (a failure moves the penalty's side); the
+    lower bound moves by 10 % of the width but at most halves.  Returns
+    (final lo, hi, widenings)."""
+    n = len(lam)
+    r = 0
+    while True:
+        m = max(n_of(lo, hi), cb.penalty_degree(n))
+        t = exact_moments(lam, lo, hi, m)
+        if np.max(np.abs(t)) > 1.01 * n:
+            move_lo = move_hi = True
+        else:
+            pen = exact_penalty(lam, lo, hi)
+            if abs(pen) <= 0.5:
+                return lo, hi, r
+            move_lo, move_hi = pen > 0, pen < 0
+        assert r < max_reexpand
+        w = hi - lo
+        if move_lo:
+            lo = max(lo - 0.1 * w, 0.5 * lo)
+        if move_hi:
+            hi = hi + 0.1 * w
+        r += 1
+
+
+def dense_spd(lam, seed=5):
+    """S = V diag(lam) V^T on a dense 4x4-block pattern (no truncation)."""
+    nn = len(lam)
+    rng = np.random.default_rng(seed)
+    V, _ = np.linalg.qr(rng.standard_normal((nn, nn)))
     Sd = V @ np.diag(lam) @ V.T
     Sd = 0.5 * (Sd + Sd.T)
-    nb, b = 6, 4
+    nb, b = nn // 4, 4
     rp = np.arange(0, nb * nb + 1, nb, dtype=np.int64)
     ci = np.tile(np.arange(nb, dtype=np.int32), nb)
     pat = g.BlockPattern(nb, b, rp, ci)
     S = pl.BlockMat(nb, b, rp, ci, g.from_dense(pat, Sd))
-    P = pl.BlockMat(nb, b, rp, ci)
+    return S, pl.BlockMat(nb, b, rp, ci), pat, Sd
+
+
+def test_penalty_degree_makes_eq6_exact_to_its_threshold():
+    # with penalty_degree(n) terms, Tr W^p from the moments is within 0.1 of
+    # the sum of f^p over the eigenvalues for any spectrum in [-1, 1] (n times
+    # the fit error is below 0.1), and with 8 terms fewer it is not trusted
+    rng = np.random.default_rng(7)
+    for n in (24, 200, 2000):
+        m = cb.penalty_degree(n)
+        assert m % 8 == 0 and cb.penalty_valid(m, n) and not cb.penalty_valid(m - 8, n)
+        lam = np.concatenate([rng.uniform(-1.0, 1.0, n - 2), [-1.0, 0.9995]])
+        pen = cb.penalty_trace(exact_moments(lam, -1.0, 1.0, m))
+        assert abs(pen - exact_penalty(lam, -1.0, 1.0)) < 0.1
+    assert cb.penalty_degree(24) < cb.penalty_degree(2000) <= cb.penalty_degree(10 ** 6) <= 1024
+
+
+@pytest.mark.parametrize("case, expect", [("inside", 0), ("near_lo", 1), ("near_hi", 1),
+                                          ("below", 1), ("far_below", 2)])
+@pytest.mark.parametrize("n_pl", [40, None])
+def test_matrix_power_bounds_follow_the_exact_eigenvalues(case, expect, n_pl):
+    # S^-1 from the bounds [0.5, 2]: an eigenvalue inside but within reach of
+    # the penalty (near_lo, near_hi) moves only that side; one outside
+    # (below) fails the growth test on the check chain and moves both; one
+    # far below (0.2) needs two widenings, the second halving the lower bound.
+    # With 40 terms (fewer than penalty_degree(24) = 48) the bounds are judged
+    # on a moments-only chain of 48 terms; with the Eq. 7 degree, on the
+    # series' own moments once it reaches 48 terms
+    lo, hi = 0.5, 2.0
+    w = hi - lo
+    lam = np.linspace(lo + 0.08 * w, hi - 0.08 * w, 24)
+    if case == "near_lo":
+        lam[0] = lo + 0.0005 * w
+    elif case == "near_hi":
+        lam[-1] = hi - 0.0005 * w
+    elif case == "below":
+        lam[0] = lo - 0.03 * w
+    elif case == "far_below":
+        lam[0] = 0.2
+    S, P, pat, Sd = dense_spd(lam)
+    tol = 1e-12
+    n_of = (lambda a, b_: n_pl) if n_pl else (lambda a, b_: cb.degree(cb.power_fn(-1.0), a, b_, tol))
+    exp_lo, exp_hi, exp_r = simulate_power_widening(lam, lo, hi, n_of, max_reexpand=6)
+    assert exp_r == expect
+    val, info = pl.matrix_power(S, -1.0, P, bounds=(lo, hi), n_pl=n_pl, tol_fit=tol, max_reexpand=6)
+    assert info["reexpansions"] == exp_r
+    assert info["lo"] == exp_lo and info["hi"] == exp_hi
+    assert info["check_terms"] == max(info["n_pl"], cb.penalty_degree(24))
+    assert abs(info["penalty"]) < 0.5
+    if case in ("near_lo", "near_hi"):
+        assert (info["lo"] < lo) == (case == "near_lo") and (info["hi"] > hi) == (case == "near_hi")
+    if case == "far_below":
+        assert info["lo"] == 0.5 * (lo - 0.1 * w)
+    if n_pl is None:
+        assert np.max(np.abs(g.to_dense(pat, val) - np.linalg.inv(Sd))) < 1e-9
+
+
+def test_matrix_power_widens_on_growth():
+    # S with its smallest eigenvalue far below the guess [0.5, 1]: the growth
+    # test fails and both sides widen (the lower one at most halved) until the
+    # spectrum is inside; the result is then S^-1 on the dense pattern
+    lam = np.linspace(0.2, 1.6, 24)
+    S, P, pat, Sd = dense_spd(lam)
     val, info = pl.matrix_power(S, -1.0, P, bounds=(0.5, 1.0), tol_fit=1e-12, max_reexpand=12)
-    lo, hi, r = 0.5, 1.0, 0
-    while True:
-        n = cb.degree(cb.power_fn(-1.0), lo, hi, 1e-12)
-        if np.max(np.abs(exact_moments(lam, lo, hi, n))) <= 1.01 * 24:
-            break
-        lo, hi = pl.widen_power(lo, hi)
-        r += 1
+    n_of = lambda a, b_: cb.degree(cb.power_fn(-1.0), a, b_, 1e-12)
+    lo, hi, r = simulate_power_widening(lam, 0.5, 1.0, n_of, max_reexpand=12)
     assert info["reexpansions"] == r >= 2
     assert info["lo"] == lo and info["hi"] == hi
     assert np.max(np.abs(g.to_dense(pat, val) - np.linalg.inv(Sd))) < 1e-9
