@@ -94,16 +94,20 @@ def s_bounds(S: Csr, lanczos_k: int = 60, margin: float = 1e-3) -> tuple[float, 
 
 
 def widen_power(lo: float, hi: float, side: str = "both") -> tuple[float, float]:
-    """Reading R7 for matrix powers: the failing side moves out by 10 % of the
-    width ('both' after a failed growth test, whose side is not trusted when
-    the bounds may be off on both sides, e.g. a default guess), the lower
-    bound at most halved so that it stays positive for non-integer or
+    """Reading R7 for matrix powers.  After a failed growth test ('both': an
+    eigenvalue clearly outside, and the bounds may be off on both sides, as
+    for a default guess) both sides move out by 10 % of the width.  After a
+    failed Eq. 6 ('lo' or 'hi': an eigenvalue at or within about 1 % of that
+    bound) only that side moves, by 2.5 % of the width: x^a is steepest at
+    the lower bound, where a larger step costs terms and precision.  The
+    lower bound at most halves, so that it stays positive for non-integer or
     negative exponents."""
     w = hi - lo
+    step = 0.1 if side == "both" else 0.025
     if side in ("lo", "both"):
-        lo = max(lo - 0.1 * w, 0.5 * lo)
+        lo = max(lo - step * w, 0.5 * lo)
     if side in ("hi", "both"):
-        hi = hi + 0.1 * w
+        hi = hi + step * w
     return lo, hi
 
 
@@ -118,7 +122,8 @@ def matrix_power(S: BlockMat, a: float, pattern: BlockMat, bounds=None, n_pl=Non
     moments of at least penalty_degree(n) terms.  A shorter series is first
     checked on a moments-only chain of that length; a longer one is checked
     on its own moments.  A failure widens the bounds (widen_power: both sides
-    after the growth test, the penalty's side after Eq. 6) and redoes the
+    by 10 % of the width after the growth test, the penalty's side by 2.5 %
+    after Eq. 6) and redoes the
     check, at most max_reexpand times; info['reexpansions'] counts the
     widenings, info['penalty'] is Tr W^p for the final bounds and
     info['check_terms'] the number of moments it was judged on."""

@@ -253,9 +253,9 @@ def test_widening_gives_the_matrix_function():
 
 def simulate_power_widening(lam, lo, hi, n_of, max_reexpand=3):
     """Reading R7 for matrix powers driven by exact eigenvalues: the growth
-    test on max(n_pl, penalty_degree(n)) terms (a failure moves both sides),
-    then Eq. 6 from the eigenvalues (a failure moves the penalty's side); the
-    lower bound moves by 10 % of the width but at most halves.  Returns
+    test on max(n_pl, penalty_degree(n)) terms (a failure moves both sides by
+    10 % of the width), then Eq. 6 from the eigenvalues (a failure moves the
+    penalty's side by 2.5 %); the lower bound at most halves.  Returns
     (final lo, hi, widenings)."""
     n = len(lam)
     r = 0
@@ -264,17 +264,19 @@ def simulate_power_widening(lam, lo, hi, n_of, max_reexpand=3):
         t = exact_moments(lam, lo, hi, m)
         if np.max(np.abs(t)) > 1.01 * n:
             move_lo = move_hi = True
+            step = 0.1
         else:
             pen = exact_penalty(lam, lo, hi)
             if abs(pen) <= 0.5:
                 return lo, hi, r
             move_lo, move_hi = pen > 0, pen < 0
+            step = 0.025
         assert r < max_reexpand
         w = hi - lo
         if move_lo:
-            lo = max(lo - 0.1 * w, 0.5 * lo)
+            lo = max(lo - step * w, 0.5 * lo)
         if move_hi:
-            hi = hi + 0.1 * w
+            hi = hi + step * w
         r += 1
 
 
@@ -312,9 +314,10 @@ def test_penalty_degree_makes_eq6_exact_to_its_threshold():
 @pytest.mark.parametrize("n_pl", [40, None])
 def test_matrix_power_bounds_follow_the_exact_eigenvalues(case, expect, n_pl):
     # S^-1 from the bounds [0.5, 2]: an eigenvalue inside but within reach of
-    # the penalty (near_lo, near_hi) moves only that side; one outside
-    # (below) fails the growth test on the check chain and moves both; one
-    # far below (0.2) needs two widenings, the second halving the lower bound.
+    # the penalty (near_lo, near_hi) moves only that side, by 2.5 % of the
+    # width; one outside (below) fails the growth test on the check chain and
+    # moves both by 10 %; one far below (0.2) needs two widenings, the second
+    # halving the lower bound.
     # With 40 terms (fewer than penalty_degree(24) = 48) the bounds are judged
     # on a moments-only chain of 48 terms; with the Eq. 7 degree, on the
     # series' own moments once it reaches 48 terms
@@ -339,8 +342,10 @@ def test_matrix_power_bounds_follow_the_exact_eigenvalues(case, expect, n_pl):
     assert info["lo"] == exp_lo and info["hi"] == exp_hi
     assert info["check_terms"] == max(info["n_pl"], cb.penalty_degree(24))
     assert abs(info["penalty"]) < 0.5
-    if case in ("near_lo", "near_hi"):
-        assert (info["lo"] < lo) == (case == "near_lo") and (info["hi"] > hi) == (case == "near_hi")
+    if case == "near_lo":
+        assert info["lo"] == lo - 0.025 * w and info["hi"] == hi
+    if case == "near_hi":
+        assert info["lo"] == lo and info["hi"] == hi + 0.025 * w
     if case == "far_below":
         assert info["lo"] == 0.5 * (lo - 0.1 * w)
     if n_pl is None:
