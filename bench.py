@@ -533,6 +533,8 @@ def main():
                                     f"N_e {sysm.n_electrons:g}",
                            form=f"float32 chain, {form_name} checked by Eq. 6, tol_fit {tol_fit:g}",
                            n_pl=n_pl, n_pl_s=info["n_pl_s"], passes=passes,
+                           s_check_terms=info["s_check_terms"],
+                           s_penalty=float(f"{info['s_penalty']:.3e}"),
                            time_to_solution_ms=round(ms_per_step, 2)),
                roofline=roof)
 

@@ -204,6 +204,14 @@ typedef struct {
      * a pass runs half its chain (n_pl / 2 - 1 products) and takes the other
      * moments from Frobenius products of the T_m it computed */
     int32_t moment_products;
+    /* chess_matrix_power, and the S chain of chess_fermi_operator and
+     * chess_eigs_in_interval: Tr W^p of Eq. 6 for the final bounds of S (NaN
+     * if not evaluated, e.g. with sinvhalf_in) and the number of moments it
+     * was judged on: the series' own n_pl_s terms, or, when that is fewer than
+     * Eq. 6 needs on this many rows (chess_degree with CHESS_FN_PENALTY), a
+     * moments-only chain of that many terms run first */
+    double s_penalty;
+    int32_t s_check_terms;
 } chess_info;
 
 /*
@@ -352,13 +360,19 @@ int chess_model_save(const chess_ctx *ctx, float *blob, int64_t n);
  *            Eq. 9) of width kT = param centred at mu = (lo + hi)/2, where the
  *            Chebyshev nodes are sparsest (the degree used for any mu);
  *            CHESS_FN_POWER: x^param (Sec. "Matrix powers"), lo > 0 needed
- *            unless param is a non-negative integer
+ *            unless param is a non-negative integer;
+ *            CHESS_FN_PENALTY: the terms with which Eq. 6 is trusted on
+ *            param rows: the smallest multiple of 8 (at most 1024) for which
+ *            param times the fit error of the penalty function (alpha = -200,
+ *            bounds -1 and 1, same grid rule) is below 0.1 (lo, hi and
+ *            tol_fit must still be valid but are not used)
  *   n_pl_out : host, receives the degree
  * Returns CHESS_E_ARG for an unknown fn, hi <= lo, tol_fit <= 0, param <= 0
- * for an occupation, lo <= 0 for a non-integer power, or a null n_pl_out;
- * CHESS_E_NOCONV when 20000 terms do not reach tol_fit.
+ * for an occupation, lo <= 0 for a non-integer power, param < 1 for
+ * CHESS_FN_PENALTY, or a null n_pl_out; CHESS_E_NOCONV when 20000 terms do
+ * not reach tol_fit.
  */
-enum { CHESS_FN_ERFC = 0, CHESS_FN_FERMI_DIRAC = 1, CHESS_FN_POWER = 2 };
+enum { CHESS_FN_ERFC = 0, CHESS_FN_FERMI_DIRAC = 1, CHESS_FN_POWER = 2, CHESS_FN_PENALTY = 3 };
 int chess_degree(int32_t fn, double param, double lo, double hi, double tol_fit, int32_t *n_pl_out);
 
 /* Fills *opts with the defaults listed above. */
@@ -403,8 +417,14 @@ int chess_fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_matr
  * with f(x) = x^a over the spectral bounds of S; non-integer or negative a
  * need a positive lower bound (else CHESS_E_NOT_SPD).  Sa_out is on `pattern`.
  * The bounds, degree and Eq. 7 threshold are those of S in opts: s_bounds,
- * n_pl_s, tol_fit_s (bounds that fail the growth test |Tr T_k| <= 1.01 n
- * are widened on both sides by 10 % of the width, up to max_reexpand times).
+ * n_pl_s, tol_fit_s.  The bounds are judged by the growth test and Eq. 6
+ * (Sec. "Determination of the eigenvalue bounds and polynomial degree") on at
+ * least the moments Eq. 6 needs on this many rows: a shorter series is first
+ * checked on a moments-only chain of that length.  Bounds that fail move out:
+ * both sides by 10 % of the width after the growth test, the penalty's side
+ * by 2.5 % after Eq. 6, the lower bound at most halved; up to max_reexpand
+ * times, else CHESS_E_BOUNDS.  info: lo, hi, n_pl, reexpansions, penalty
+ * (= s_penalty), s_check_terms, chain_steps (check chains included).
  */
 int chess_matrix_power(chess_ctx *ctx, const chess_matrix *S, double a,
                        const chess_pattern *pattern, chess_matrix *Sa_out,

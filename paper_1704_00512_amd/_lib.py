@@ -16,7 +16,7 @@ CHESS_OK = 0
 CHESS_F64, CHESS_F32, CHESS_BF16, CHESS_BF16X3 = 0, 1, 2, 3
 CHESS_ERFC, CHESS_FERMI_DIRAC = 0, 1
 CHESS_BOUNDS_GERSHGORIN, CHESS_BOUNDS_LANCZOS, CHESS_BOUNDS_LEARNED, CHESS_BOUNDS_LEARNED_LANCZOS = 0, 1, 2, 3
-CHESS_FN_ERFC, CHESS_FN_FERMI_DIRAC, CHESS_FN_POWER = 0, 1, 2
+CHESS_FN_ERFC, CHESS_FN_FERMI_DIRAC, CHESS_FN_POWER, CHESS_FN_PENALTY = 0, 1, 2, 3
 
 ERRORS = {
     -1: "CHESS_E_ARG", -2: "CHESS_E_PATTERN", -3: "CHESS_E_NOT_SPD", -4: "CHESS_E_BOUNDS",
@@ -67,7 +67,8 @@ class chess_info(ctypes.Structure):
                 ("kt_used", ctypes.c_double), ("kt_halvings", ctypes.c_int32),
                 ("homo", ctypes.c_double), ("lumo", ctypes.c_double),
                 ("ms_chain_kernel_acc", ctypes.c_double), ("kernel_variant_moments", ctypes.c_int32),
-                ("tile_rows", ctypes.c_int32), ("moment_products", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("moment_products", ctypes.c_int32),
+                ("s_penalty", ctypes.c_double), ("s_check_terms", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -422,13 +422,15 @@ def chess_bcsr_to_ssf(b: int, row_ptr, col_idx, val):
 
 
 _FN = {"erfc": _lib.CHESS_FN_ERFC, "fermi_dirac": _lib.CHESS_FN_FERMI_DIRAC,
-       "power": _lib.CHESS_FN_POWER}
+       "power": _lib.CHESS_FN_POWER, "penalty": _lib.CHESS_FN_PENALTY}
 
 
 def chess_degree(fn: str, param: float, lo: float, hi: float, tol_fit: float) -> int:
     """Eq. 7's degree for an occupation of width param (fn "erfc" or
-    "fermi_dirac", centred on [lo, hi]) or for x^param (fn "power"); host
-    only.  Raises ChessError with the library's code."""
+    "fermi_dirac", centred on [lo, hi]) or for x^param (fn "power"); with fn
+    "penalty", the terms with which Eq. 6 is trusted on param rows (lo, hi
+    and tol_fit unused).  Host only.  Raises ChessError with the library's
+    code."""
     L = _lib.load()
     out = ctypes.c_int32(0)
     rc = L.chess_degree(_FN[fn], float(param), float(lo), float(hi), float(tol_fit),

@@ -1577,12 +1577,25 @@ static bool growth_ok(const std::vector<double> &t, int64_t n) {
 }
 
 // x^a by the chain on S~ (U-form accumulator -> acc, transposed storage).
+// The bounds are judged by the growth test and Eq. 6 on at least
+// penalty_degree(n) moments: a shorter series is first checked on a
+// moments-only chain of that length, a longer one on its own moments.  A
+// failed growth test widens both sides by 10 % of the width (its side is not
+// trusted when both bounds may be off, as for a default guess); a failed
+// Eq. 6 (an eigenvalue at or within about 1 % of a bound) moves only the
+// penalty's side, by 2.5 % of the width, since x^a is steepest at the lower
+// bound, where a larger step costs terms and precision.  The lower bound at
+// most halves, so it stays positive.  The check chain multiplies operands in the storage
+// precision (float32 in the bfloat16 forms).
 struct PowerResult {
     double lo, hi;
     int n_pl;
     int reexp;
     double kernel_ms;
     int variant = -1;
+    double penalty = NAN;  // Tr W^p for the final bounds (NaN if not evaluated)
+    int check_terms = 0;   // moments the final bounds were judged on
+    int products = 0;      // product launches, check chains included
 };
 
 static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *S,
@@ -1592,6 +1605,8 @@ static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *
     hipStream_t st = ctx->stream;
     DevBuf St(sizeof(double) * (size_t)PS->nnzb * PS->b * PS->b);
     PowerResult r{lo, hi, 0, 0, 0.0};
+    const int64_t n = PK->n();
+    const int n_check = hostmath::penalty_degree(n);
     for (int attempt = 0;; ++attempt) {
         double sigma, tau;
         hostmath::scale_shift(r.lo, r.hi, &sigma, &tau);
@@ -1605,35 +1620,66 @@ static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *
                 n_pl = std::max(n_pl, m);
             }
         }
-        std::vector<double> coef((size_t)powers.size() * n_pl);
-        for (size_t q = 0; q < powers.size(); ++q) {
-            const double a = powers[q];
-            auto c = hostmath::cheb_coeffs([a](double x) { return std::pow(x, a); }, r.lo, r.hi, n_pl);
-            std::copy(c.begin(), c.end(), coef.begin() + q * n_pl);
+        hostmath::BoundsCheck chk;
+        if (n_pl < n_check) {
+            // too few terms for Eq. 6: judge the bounds on a moments-only
+            // chain of n_check terms before summing the series
+            std::vector<double> cm;
+            ChainRequest cq;
+            cq.label = "S check chain";
+            cq.PM = PS;
+            cq.Mt = St.as<double>();
+            cq.PK = PK;
+            cq.n_pl = n_check;
+            cq.dtype = storage_dtype(o.precision);
+            // the storage precision's own operands, also in the bfloat16
+            // forms: rounding the operands to bfloat16 puts noise of order
+            // 0.01 sqrt(n) on Tr W^p, past the threshold of 0.5 at several
+            // thousand rows
+            cq.opmode = 0;
+            cq.moments = &cm;
+            run_chain(ctx, cq);
+            r.kernel_ms += cq.kernel_ms;
+            r.products += cq.products;
+            chk = hostmath::bounds_check(cm, n);
         }
-        std::vector<double> mom;
-        ChainRequest rq;
-        rq.label = "S chain";
-        rq.PM = PS;
-        rq.Mt = St.as<double>();
-        rq.PK = PK;
-        rq.n_pl = n_pl;
-        rq.nq = (int)powers.size();
-        rq.coef = coef.data();
-        for (size_t q = 0; q < powers.size(); ++q) rq.acc[q] = acc[q];
-        rq.dtype = storage_dtype(o.precision);
-        rq.opmode = operand_mode(o.precision);
-        rq.moments = &mom;
-        run_chain(ctx, rq);
+        if (n_pl >= n_check || chk.ok) {
+            std::vector<double> coef((size_t)powers.size() * n_pl);
+            for (size_t q = 0; q < powers.size(); ++q) {
+                const double a = powers[q];
+                auto c = hostmath::cheb_coeffs([a](double x) { return std::pow(x, a); }, r.lo, r.hi, n_pl);
+                std::copy(c.begin(), c.end(), coef.begin() + q * n_pl);
+            }
+            std::vector<double> mom;
+            ChainRequest rq;
+            rq.label = "S chain";
+            rq.PM = PS;
+            rq.Mt = St.as<double>();
+            rq.PK = PK;
+            rq.n_pl = n_pl;
+            rq.nq = (int)powers.size();
+            rq.coef = coef.data();
+            for (size_t q = 0; q < powers.size(); ++q) rq.acc[q] = acc[q];
+            rq.dtype = storage_dtype(o.precision);
+            rq.opmode = operand_mode(o.precision);
+            rq.moments = &mom;
+            run_chain(ctx, rq);
+            r.kernel_ms += rq.kernel_ms;
+            r.products += rq.products;
+            r.variant = rq.variant;
+            if (n_pl >= n_check) chk = hostmath::bounds_check(mom, n);
+        }
         r.n_pl = n_pl;
-        r.kernel_ms += rq.kernel_ms;
-        r.variant = rq.variant;
-        if (growth_ok(mom, PK->n())) break;
-        if (attempt >= o.max_reexpand) CHESS_THROW(CHESS_E_BOUNDS, "spectral bounds [%g, %g] still fail the growth test", r.lo, r.hi);
-        // widen both sides by 10% of the width (the lower bound stays positive)
+        r.penalty = chk.penalty;
+        r.check_terms = std::max(n_pl, n_check);
+        if (chk.ok) break;
+        if (attempt >= o.max_reexpand)
+            CHESS_THROW(CHESS_E_BOUNDS, "spectral bounds [%g, %g] still fail after %d widenings", r.lo, r.hi, attempt);
         const double w = r.hi - r.lo;
-        r.hi += 0.1 * w;
-        r.lo = std::max(r.lo - 0.1 * w, 0.5 * r.lo);
+        const int side = chk.valid ? chk.side : 0;
+        const double step = chk.valid ? 0.025 : 0.1;
+        if (side <= 0) r.lo = std::max(r.lo - step * w, 0.5 * r.lo);
+        if (side >= 0) r.hi += step * w;
         r.reexp++;
     }
     return r;
@@ -1653,6 +1699,10 @@ static void set_err(chess_ctx *ctx, const Error &e) { ctx->err = e.msg; }
 struct Frame {
     DevBuf accX, X, Hp;
     PowerResult s;
+    // the interval of S the call started from (given, or Gershgorin/Lanczos),
+    // before any widening by the checks: the predictor's features describe
+    // the spectrum of S with it, as in its training data
+    double s_lo0 = NAN, s_hi0 = NAN;
     double ms_s = 0, ms_transform = 0;
 };
 
@@ -1668,9 +1718,13 @@ static void build_frame(chess_ctx *ctx, const Pattern *PH, const double *H, cons
         // does not change): no S chain; its bounds are those given, if any
         transpose_into(ctx, PK, (const double *)o.sinvhalf_in, F.accX.as<double>());
         F.s = PowerResult{o.s_bounds[0], o.s_bounds[1], 0, 0, 0.0, -1};
+        F.s_lo0 = o.s_bounds[0];
+        F.s_hi0 = o.s_bounds[1];
     } else {
         double slo, shi;
         s_bounds(ctx, PS, S, o, true, &slo, &shi);
+        F.s_lo0 = slo;
+        F.s_hi0 = shi;
         double *accs[1] = {F.accX.as<double>()};
         F.s = power_chain(ctx, PS, S, PK, {-0.5}, o, o.n_pl_s, o.tol_fit_s, accs, slo, shi);
     }
@@ -1868,7 +1922,7 @@ static void fill_info_defaults(chess_info *info) {
     std::memset(info, 0, sizeof(*info));
     const double nan = std::numeric_limits<double>::quiet_NaN();
     info->mu = info->lo = info->hi = info->s_lo = info->s_hi = nan;
-    info->tr_ks = info->ne_chain = info->penalty = nan;
+    info->tr_ks = info->ne_chain = info->penalty = info->s_penalty = nan;
     info->pred_lo = info->pred_hi = info->pred_mu = nan;
     info->energy = info->energy_wide = info->homo = info->lumo = nan;
     info->kernel_variant = -1;
@@ -1939,9 +1993,9 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         // Gershgorin interval) and a predicted mu bracket; Eq. 6 and the
         // growth test still judge the bounds, bisection still judges mu
         const double t0 = now_ms();
-        if (!(std::isfinite(F.s.lo) && std::isfinite(F.s.hi)))
+        if (!(std::isfinite(F.s_lo0) && std::isfinite(F.s_hi0)))
             CHESS_THROW(CHESS_E_ARG, "learned bounds with a given S^-1/2 need s_bounds");
-        compute_features(ctx, PH, F.Hp.as<double>(), PK, F.s.lo, F.s.hi, n_e, kT, fe);
+        compute_features(ctx, PH, F.Hp.as<double>(), PK, F.s_lo0, F.s_hi0, n_e, kT, fe);
         predict(ctx, fe, pred);
         const Model &M = ctx->model;
         const double w = 0.5 * (fe.g_hi - fe.g_lo);
@@ -2166,7 +2220,9 @@ static void fermi_operator(chess_ctx *ctx, const chess_matrix *H, const chess_ma
         info->passes = passes;
         info->bisect_iters = iters;
         info->reexpansions = reexp + F.s.reexp;
-        info->chain_steps = products + std::max(F.s.n_pl - 2, 0);
+        info->s_penalty = F.s.penalty;
+        info->s_check_terms = F.s.check_terms;
+        info->chain_steps = products + F.s.products;
         info->moment_products = moment_products;
         info->ms_total = t_end - t_begin;
         info->ms_setup = t_setup - t_begin;
@@ -2221,7 +2277,9 @@ static void matrix_power(chess_ctx *ctx, const chess_matrix *S, double a,
         info->n_pl = info->n_pl_s = r.n_pl;
         info->passes = 1;
         info->reexpansions = r.reexp;
-        info->chain_steps = std::max(r.n_pl - 2, 0);
+        info->penalty = info->s_penalty = r.penalty;
+        info->s_check_terms = r.check_terms;
+        info->chain_steps = r.products;
         info->ms_total = now_ms() - t0;
         info->ms_chain_kernel = r.kernel_ms;
         info->kernel_variant = r.variant;
@@ -2298,6 +2356,8 @@ static void eigs_in_interval(chess_ctx *ctx, const chess_matrix *H, const chess_
         info->passes = 1 + reexp;
         info->reexpansions = reexp;
         info->penalty = penalty;
+        info->s_penalty = F.s.penalty;
+        info->s_check_terms = F.s.check_terms;
         info->ms_total = now_ms() - t0;
         info->ms_chain_kernel = kernel_ms;
         info->kernel_variant = variant;
@@ -2777,7 +2837,7 @@ static void features_api(chess_ctx *ctx, const chess_matrix *H, const chess_matr
     Frame F;
     build_frame(ctx, PH, (const double *)H->val, PS, (const double *)S->val, PK, o, F);
     Features fe;
-    compute_features(ctx, PH, F.Hp.as<double>(), PK, F.s.lo, F.s.hi, n_e, kT, fe);
+    compute_features(ctx, PH, F.Hp.as<double>(), PK, F.s_lo0, F.s_hi0, n_e, kT, fe);
     std::memcpy(feat, fe.f, sizeof(fe.f));
     if (gersh) {
         gersh[0] = fe.g_lo;
@@ -2844,6 +2904,14 @@ int chess_degree(int32_t fn, double param, double lo, double hi, double tol_fit,
     if (fn == CHESS_FN_ERFC || fn == CHESS_FN_FERMI_DIRAC) {
         if (!(param > 0)) return CHESS_E_ARG;
         f = chess::occupation(fn == CHESS_FN_ERFC ? CHESS_ERFC : CHESS_FERMI_DIRAC, 0.5 * (lo + hi), param);
+    } else if (fn == CHESS_FN_PENALTY) {
+        if (!(param >= 1) || param > 9.0e18) return CHESS_E_ARG;
+        try {
+            *n_pl_out = chess::hostmath::penalty_degree((long long)param);
+            return CHESS_OK;
+        } catch (...) {
+            return CHESS_E_OOM;
+        }
     } else if (fn == CHESS_FN_POWER) {
         const bool whole = param >= 0 && std::floor(param) == param;
         if (!whole && !(lo > 0)) return CHESS_E_ARG;

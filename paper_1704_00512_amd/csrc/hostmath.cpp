@@ -242,6 +242,13 @@ double penalty_trace(const std::vector<double> &t, double alpha, double *fit_err
     return s;
 }
 
+int penalty_degree(long long n_rows) {
+    const double alpha = -200.0;
+    Fn fp = [alpha](double x) { return std::exp(alpha * (x + 1.0)) - std::exp(-alpha * (x - 1.0)); };
+    const int m = degree(fp, -1.0, 1.0, 0.1 / (double)std::max(n_rows, 1LL), 8, 1024);
+    return m < 0 ? 1024 : m;
+}
+
 BoundsCheck bounds_check(const std::vector<double> &t, long long n_rows) {
     BoundsCheck r;
     bool grows = false;

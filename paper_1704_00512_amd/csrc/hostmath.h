@@ -109,6 +109,12 @@ struct BoundsCheck {
 };
 BoundsCheck bounds_check(const std::vector<double> &moments, long long n_rows);
 
+// Terms with which Eq. 6 is trusted on n_rows rows: the fewest multiple of 8
+// (at most 1024) whose fit of f^p (alpha = -200, bounds -1 and 1) has
+// n_rows * fit error < 0.1.  A matrix-power series shorter than this is
+// judged on a moments-only chain of this many terms before it is summed.
+int penalty_degree(long long n_rows);
+
 // Moves the failing side out by 10 % of the width (side 0: both).
 inline void widen(int side, double *lo, double *hi) {
     const double w = *hi - *lo;

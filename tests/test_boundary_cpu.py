@@ -212,10 +212,19 @@ def test_degree_rule_matches_the_oracle(lib, fn, param, lo, hi, tol):
     assert cb.degree(f, lo, hi, tol, m_start=start, m_max=20000) == m
 
 
+@pytest.mark.parametrize("n_rows", [1, 24, 2400, 80000, 347466, 10 ** 9])
+def test_penalty_terms_match_the_oracle(lib, n_rows):
+    # the number of moments Eq. 6 is judged on for a matrix power (a shorter
+    # series is checked on a moments-only chain of this length first)
+    from oracle import chebyshev as cb
+    from paper_1704_00512_amd import chess_degree
+    assert chess_degree("penalty", n_rows, -1.0, 1.0, 1.0) == cb.penalty_degree(n_rows)
+
+
 def test_degree_rule_errors(lib):
     from paper_1704_00512_amd import ChessError, chess_degree
     for args in (("erfc", 0.0, -1, 1, 1e-6), ("erfc", 0.01, 1, -1, 1e-6), ("erfc", 0.01, -1, 1, 0.0),
-                 ("power", -0.5, -0.1, 1.0, 1e-6)):
+                 ("power", -0.5, -0.1, 1.0, 1e-6), ("penalty", 0.5, -1.0, 1.0, 1.0)):
         with pytest.raises(ChessError) as e:
             chess_degree(*args)
         assert e.value.name == "CHESS_E_ARG"

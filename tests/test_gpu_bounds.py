@@ -9,6 +9,12 @@ and polynomial degree"):
   * the default-bounds search of matrix powers (the paper's Fig. 9 "bounds
     default" [0.5, 1]): chess_matrix_power widening by the growth test, final
     bounds, widenings, degree and S^-1 against the oracle;
+  * the Eq. 6 check of matrix powers on designed spectra (an eigenvalue of S
+    within the penalty's reach of a bound, just outside it, far below it),
+    with a series shorter than the moments Eq. 6 needs (judged on a
+    moments-only chain first) and with the Eq. 7 degree (judged on its own
+    moments): widenings, sides, final bounds, check length, Tr W^p and S^-1
+    against the oracle;
   * the Eq. 7 degrees chosen inside full calls equal the oracle's.
 """
 import numpy as np
@@ -111,6 +117,63 @@ def test_default_bounds_inverse_matches_the_oracle(gpu_ctx):
     print(f"[gpu-bounds] S^-1: widenings {ig['reexpansions']}, bounds [{ig['lo']:.4f}, "
           f"{ig['hi']:.4f}], n_pl {ig['n_pl']}, max|S^-1 - oracle| = {err:.2e}", flush=True)
     assert err < 1e-10
+
+
+def dense_spd(lam, seed=5):
+    """S = V diag(lam) V^T on a dense pattern of 4x4 blocks (no truncation)."""
+    nn = len(lam)
+    rng = np.random.default_rng(seed)
+    V, _ = np.linalg.qr(rng.standard_normal((nn, nn)))
+    Sd = V @ np.diag(lam) @ V.T
+    Sd = 0.5 * (Sd + Sd.T)
+    nb = nn // 4
+    rp = np.arange(0, nb * nb + 1, nb, dtype=np.int64)
+    ci = np.tile(np.arange(nb, dtype=np.int32), nb)
+    pat = g.BlockPattern(nb, 4, rp, ci)
+    vals = g.from_dense(pat, Sd)
+    return opl.BlockMat(nb, 4, rp, ci, vals), opl.BlockMat(nb, 4, rp, ci), pat, vals, Sd
+
+
+@pytest.mark.parametrize("precision, tol", [("f64", 1e-10), ("f32", 1e-5)])
+@pytest.mark.parametrize("case, expect", [("inside", 0), ("near_lo", 1), ("near_hi", 1),
+                                          ("below", 1), ("far_below", 2)])
+@pytest.mark.parametrize("n_pl", [40, None])
+def test_matrix_power_bound_check_matches_the_oracle(gpu_ctx, precision, tol, case, expect, n_pl):
+    # S^-1 from the bounds [0.5, 2] of a 24-row S whose spectrum is placed
+    # against them; 40 terms are fewer than the 48 that Eq. 6 needs on 24
+    # rows, so those bounds are judged on a moments-only chain of 48 terms
+    lo, hi = 0.5, 2.0
+    w = hi - lo
+    lam = np.linspace(lo + 0.08 * w, hi - 0.08 * w, 24)
+    if case == "near_lo":
+        lam[0] = lo + 0.0005 * w
+    elif case == "near_hi":
+        lam[-1] = hi - 0.0005 * w
+    elif case == "below":
+        lam[0] = lo - 0.03 * w
+    elif case == "far_below":
+        lam[0] = 0.2
+    S, P, pat, vals, Sd = dense_spd(lam)
+    kw = dict(tol_fit=1e-12, max_reexpand=6)
+    print(f"[gpu-bounds] oracle S^-1 {case} n_pl={n_pl}", flush=True)
+    vo, io = opl.matrix_power(S, -1.0, P, bounds=(lo, hi), n_pl=n_pl, **kw)
+    assert io["reexpansions"] == expect
+    extra = {} if n_pl is None else dict(n_pl_s=n_pl)
+    print(f"[gpu-bounds] library S^-1 {case} n_pl={n_pl} {precision}", flush=True)
+    vg, ig = chess_matrix_power(gpu_ctx, dt(vals), gpat(pat), -1.0, gpat(pat), precision=precision,
+                                s_bounds=(lo, hi), tol_fit_s=1e-12, max_reexpand=6, **extra)
+    assert ig["reexpansions"] == io["reexpansions"]
+    assert abs(ig["lo"] - io["lo"]) < 1e-14 and abs(ig["hi"] - io["hi"]) < 1e-14
+    assert ig["n_pl"] == io["n_pl"]
+    assert ig["s_check_terms"] == io["check_terms"] == max(io["n_pl"], cb.penalty_degree(24))
+    assert ig["penalty"] == ig["s_penalty"]
+    assert abs(ig["s_penalty"] - io["penalty"]) < (1e-10 if precision == "f64" else 1e-4)
+    ref = np.max(np.abs(vo))
+    err = float(np.max(np.abs(vg.cpu().numpy() - vo))) / ref
+    print(f"[gpu-bounds] widenings {ig['reexpansions']}, bounds [{ig['lo']:.4f}, {ig['hi']:.4f}], "
+          f"check terms {ig['s_check_terms']}, penalty {ig['s_penalty']:.3e}, "
+          f"max|S^-1 - oracle| / max|S^-1| = {err:.2e}", flush=True)
+    assert err < tol
 
 
 def test_degrees_chosen_in_full_calls_match_the_oracle(gpu_ctx):
