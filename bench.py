@@ -306,7 +306,9 @@ def bench_batched(args):
                dtype="f32", data="synthetic",
                config=dict(workload=f"batched48: {len(ss)} systems, 200-4000 atoms, b 4|9, "
                                     f"{rows} rows in total, kT 0.005, half filling",
-                           n_pl_min=min(npl), n_pl_max=max(npl)),
+                           n_pl_min=min(npl), n_pl_max=max(npl),
+                           s_widened=sum(r["info"]["reexpansions"] > 0 for r in res),
+                           n_pl_s_max=max(r["info"]["n_pl_s"] for r in res)),
                sequential_single_system_ms=round(ms_seq, 1),
                speedup_vs_sequential=round(ms_seq / ms_b, 2))
     print(json.dumps(out), flush=True)

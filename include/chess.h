@@ -239,12 +239,17 @@ typedef struct {
  *   ne_trial    : host, 3 doubles or NULL: N(mu_trial[q]) from the moments
  *   info        : host or NULL: mu = the root of N(mu) = N_e from the moments,
  *                 lo, hi, s_lo, s_hi, n_pl, n_pl_s, penalty, tr_ks (of K at
- *                 mu_trial[1]), ne_chain = N(mu_trial[1]); ms_total and
+ *                 mu_trial[1]), ne_chain = N(mu_trial[1]), s_penalty,
+ *                 s_check_terms, reexpansions (of S); ms_total and
  *                 ms_chain_kernel are those of the whole call
- * A system whose bounds fail Eq. 6 or the growth test is redone, after the
- * others, in a batch of its own with the Gershgorin interval (info->fallback
- * bit 0 set); CHESS_E_BOUNDS only if the Gershgorin interval itself fails.
- * opts apply to every system.
+ * The bounds of each S are judged as in chess_matrix_power, on one
+ * moments-only check chain over the batch (each system to the terms Eq. 6
+ * needs on its rows); failing systems widen and the check runs again, at
+ * most max_reexpand times, else CHESS_E_BOUNDS.
+ * A system whose bounds of H' fail Eq. 6 or the growth test is redone, after
+ * the others, in a batch of its own with the Gershgorin interval
+ * (info->fallback bit 0 set); CHESS_E_BOUNDS only if the Gershgorin interval
+ * itself fails.  opts apply to every system.
  */
 typedef struct {
     const chess_matrix *H;

@@ -1598,6 +1598,15 @@ struct PowerResult {
     int products = 0;      // product launches, check chains included
 };
 
+// The widening of a matrix power's bounds after a failed check (see above).
+static void widen_power(const hostmath::BoundsCheck &chk, double *lo, double *hi) {
+    const double w = *hi - *lo;
+    const int side = chk.valid ? chk.side : 0;
+    const double step = chk.valid ? 0.025 : 0.1;
+    if (side <= 0) *lo = std::max(*lo - step * w, 0.5 * *lo);
+    if (side >= 0) *hi += step * w;
+}
+
 static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *S,
                                const Pattern *PK, const std::vector<double> &powers,
                                const chess_opts &o, int n_pl_fixed, double tol, double *const *acc,
@@ -1675,11 +1684,7 @@ static PowerResult power_chain(chess_ctx *ctx, const Pattern *PS, const double *
         if (chk.ok) break;
         if (attempt >= o.max_reexpand)
             CHESS_THROW(CHESS_E_BOUNDS, "spectral bounds [%g, %g] still fail after %d widenings", r.lo, r.hi, attempt);
-        const double w = r.hi - r.lo;
-        const int side = chk.valid ? chk.side : 0;
-        const double step = chk.valid ? 0.025 : 0.1;
-        if (side <= 0) r.lo = std::max(r.lo - step * w, 0.5 * r.lo);
-        if (side >= 0) r.hi += step * w;
+        widen_power(chk, &r.lo, &r.hi);
         r.reexp++;
     }
     return r;
@@ -2511,9 +2516,68 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
     std::vector<double> slo(nsys), shi(nsys), ssig(nsys), stau(nsys);
     std::vector<int> npls(nsys);
     int npls_max = 2;
-    for (int s = 0; s < nsys; ++s) {
+    DevBuf dsig(sizeof(double) * nsys), dtau(sizeof(double) * nsys);
+    DevBuf St(Ss.bytes);
+    auto scale_all = [&]() {
+        for (int s = 0; s < nsys; ++s) hostmath::scale_shift(slo[s], shi[s], &ssig[s], &stau[s]);
+        HIPCHECK(hipMemcpyAsync(dsig.p, ssig.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(dtau.p, stau.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, st));
+        HIPCHECK(launch_scale_shift_rows(b, PS->nnzb, PS->d_brow.as<int32_t>(), PS->d_ci.as<int32_t>(),
+                                         d_row_sys.as<int32_t>(), dsig.as<double>(), dtau.as<double>(),
+                                         Ss.as<double>(), St.as<double>(), st));
+        // the host vectors are rewritten by the next widening
+        HIPCHECK(hipStreamSynchronize(st));
+    };
+    for (int s = 0; s < nsys; ++s)
         s_bounds(ctx, PSs[s], (const double *)items[idx[s]].S->val, o, true, &slo[s], &shi[s]);
-        hostmath::scale_shift(slo[s], shi[s], &ssig[s], &stau[s]);
+    // the intervals the predictor's features describe S with (before any widening)
+    const std::vector<double> slo0 = slo, shi0 = shi;
+    // Eq. 6 and the growth test on every system's S, as in single calls: one
+    // moments-only chain over the batch, each system running the
+    // penalty_degree(n) terms Eq. 6 needs on its rows; failing systems widen
+    // (the matrix-power rule) and the check runs again
+    std::vector<double> spen(nsys, NAN);
+    std::vector<int> sre(nsys, 0), nchk(nsys);
+    int nchk_max = 2, check_products = 0;
+    for (int s = 0; s < nsys; ++s) {
+        nchk[s] = hostmath::penalty_degree(PKs[s]->n());
+        nchk_max = std::max(nchk_max, nchk[s]);
+    }
+    for (int attempt = 0;; ++attempt) {
+        scale_all();
+        std::vector<double> cmom;
+        BatchChain cc;
+        cc.PM = PS;
+        cc.PK = PK;
+        cc.Mt = St.as<double>();
+        cc.n_pl = nchk_max;
+        cc.nq = 0;
+        cc.dtype = dtype;
+        cc.opmode = 0;  // the storage precision's operands, as in power_chain
+        cc.row0 = &row0;
+        cc.d_row_sys = d_row_sys.as<int32_t>();
+        cc.sys_npl = &nchk;
+        cc.use_graph = use_graph;
+        cc.moments = &cmom;
+        run_chain_batched(ctx, cc);
+        check_products += std::max(nchk_max - 2, 0);
+        bool all_ok = true;
+        for (int s = 0; s < nsys; ++s) {
+            std::vector<double> t(nchk[s]);
+            for (int k = 0; k < nchk[s]; ++k) t[k] = cmom[(size_t)k * nsys + s];
+            const hostmath::BoundsCheck chk = hostmath::bounds_check(t, PKs[s]->n());
+            spen[s] = chk.penalty;
+            if (chk.ok) continue;
+            if (attempt >= o.max_reexpand)
+                CHESS_THROW(CHESS_E_BOUNDS, "system %d: bounds of S [%g, %g] still fail after %d widenings", idx[s],
+                            slo[s], shi[s], attempt);
+            widen_power(chk, &slo[s], &shi[s]);
+            sre[s]++;
+            all_ok = false;
+        }
+        if (all_ok) break;
+    }
+    for (int s = 0; s < nsys; ++s) {
         int m = o.n_pl_s;
         if (m <= 0) {
             m = 1;
@@ -2535,12 +2599,6 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
             }
         return tab;
     };
-    DevBuf dsig(sizeof(double) * nsys), dtau(sizeof(double) * nsys);
-    HIPCHECK(hipMemcpyAsync(dsig.p, ssig.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, st));
-    HIPCHECK(hipMemcpyAsync(dtau.p, stau.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, st));
-    DevBuf St(Ss.bytes);
-    HIPCHECK(launch_scale_shift_rows(b, PS->nnzb, PS->d_brow.as<int32_t>(), PS->d_ci.as<int32_t>(), d_row_sys.as<int32_t>(),
-                                     dsig.as<double>(), dtau.as<double>(), Ss.as<double>(), St.as<double>(), st));
     const std::vector<double> stab = coef_table(2, npls_max, npls, [&](int s, int q, int m) {
         const double a = q == 0 ? -0.5 : -1.0;
         return hostmath::cheb_coeffs([a](double x) { return std::pow(x, a); }, slo[s], shi[s], m);
@@ -2600,7 +2658,7 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
         if (!(std::isfinite(o.bounds[0]) && std::isfinite(o.bounds[1])) &&
             (o.bounds_mode == CHESS_BOUNDS_LEARNED || o.bounds_mode == CHESS_BOUNDS_LEARNED_LANCZOS)) {
             Features fe;
-            compute_features(ctx, PHs[s], Hp, PKs[s], slo[s], shi[s], it.n_electrons, it.kT, fe);
+            compute_features(ctx, PHs[s], Hp, PKs[s], slo0[s], shi0[s], it.n_electrons, it.kT, fe);
             double pr[3];
             predict(ctx, fe, pr);
             const double w = 0.5 * (fe.g_hi - fe.g_lo);
@@ -2752,7 +2810,10 @@ static void batched_group(chess_ctx *ctx, const std::vector<int> &idx, const che
             info->n_pl_s = npls[s];
             info->passes = 1;
             info->bisect_iters = iters[s];
-            info->chain_steps = std::max(npl_max - 2, 0) + std::max(npls_max - 2, 0);
+            info->chain_steps = std::max(npl_max - 2, 0) + std::max(npls_max - 2, 0) + check_products;
+            info->reexpansions = sre[s];
+            info->s_penalty = spen[s];
+            info->s_check_terms = nchk[s];
             info->kernel_variant = hc.variant;
             info->pred_lo = preds[s][0];
             info->pred_hi = preds[s][1];

@@ -72,6 +72,58 @@ def test_batched_matches_oracle_per_system(gpu_ctx, precision, tol):
         assert r["ne_trial"][0] < r["ne_trial"][1] < r["ne_trial"][2]
 
 
+def designed_s_system(lam, seed):
+    """24 rows, dense pattern of 4x4 blocks: S = V diag(lam) V^T, H a small
+    symmetric matrix around -0.5."""
+    nn = len(lam)
+    rng = np.random.default_rng(seed)
+    V, _ = np.linalg.qr(rng.standard_normal((nn, nn)))
+    Sd = V @ np.diag(lam) @ V.T
+    Hd = 0.05 * rng.standard_normal((nn, nn)) - 0.5 * np.eye(nn)
+    nb = nn // 4
+    rp = np.arange(0, nb * nb + 1, nb, dtype=np.int64)
+    ci = np.tile(np.arange(nb, dtype=np.int32), nb)
+    pat = g.BlockPattern(nb, 4, rp, ci)
+    return pat, g.from_dense(pat, 0.5 * (Sd + Sd.T)), g.from_dense(pat, 0.5 * (Hd + Hd.T))
+
+
+def test_batched_s_bounds_are_judged_as_in_single_calls(gpu_ctx):
+    # every system's S in a batch gets the check of a single matrix power:
+    # from the given interval [0.5, 2] with 40 terms (fewer than the 48 that
+    # Eq. 6 needs on 24 rows), an eigenvalue within the penalty's reach of
+    # the lower bound moves it by 2.5 % of the width, one below it moves both
+    # bounds by 10 %, and a spectrum well inside keeps them
+    lo, hi = 0.5, 2.0
+    w = hi - lo
+    cases = []
+    for k, case in enumerate(("near_lo", "below", "inside")):
+        lam = np.linspace(lo + 0.08 * w, hi - 0.08 * w, 24)
+        if case == "near_lo":
+            lam[0] = lo + 0.0005 * w
+        elif case == "below":
+            lam[0] = lo - 0.03 * w
+        cases.append(designed_s_system(lam, 60 + k))
+    args = []
+    for pat, Sv, Hv in cases:
+        bp = BlockPattern.from_host(4, pat.row_ptr, pat.col_idx)
+        args.append(dict(H=dv(Hv), pat_h=bp, S=dv(Sv), pat_s=bp, pattern=bp, n_electrons=12.0,
+                         kT=0.02, mu_trial=(-0.6, -0.5, -0.4)))
+    print("[batched] three designed S spectra, s_bounds [0.5, 2], n_pl_s 40", flush=True)
+    res = chess_fermi_operator_batched(gpu_ctx, args, precision="f64", bounds_mode="gershgorin",
+                                       s_bounds=(lo, hi), n_pl_s=40)
+    expect = (1, 1, 0)
+    for (pat, Sv, _), r, e in zip(cases, res, expect):
+        inf = r["info"]
+        P = bm(pat)
+        X, io = opl.matrix_power(bm(pat, Sv), -0.5, P, bounds=(lo, hi), n_pl=40)
+        assert io["reexpansions"] == e
+        assert inf["reexpansions"] == io["reexpansions"]
+        assert abs(inf["s_lo"] - io["lo"]) < 1e-14 and abs(inf["s_hi"] - io["hi"]) < 1e-14
+        assert inf["s_check_terms"] == io["check_terms"] == 48
+        assert abs(inf["s_penalty"] - io["penalty"]) < 1e-10
+        assert np.max(np.abs(r["Sinvhalf"].cpu().numpy() - X)) < 1e-10
+
+
 def test_graph_and_eager_launches_agree_bitwise(gpu_ctx, monkeypatch):
     ss = systems()
     r_graph = chess_fermi_operator_batched(gpu_ctx, batch_args(ss), precision="f32",
