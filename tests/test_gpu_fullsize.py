@@ -79,11 +79,12 @@ def test_large80k_chain_sampled_columns(gpu_ctx):
 
 
 def test_large80k_long_chain_sampled_columns(gpu_ctx):
-    # the benchmark's chain length and coefficients: the float32 chain over
-    # the Eq. 7 degree for the erfc occupation at kT 0.003 Ha and tol_fit 1e-6
-    # (about 2250 terms), bounds 1 % outside the extreme eigenvalues of H,
-    # one sum at a mu inside the spectrum; 12 sampled columns against the
-    # oracle's float64 column recursion
+    # at least the benchmark's chain length, with its kind of coefficients:
+    # the float32 chain over the Eq. 7 degree for the erfc occupation at kT
+    # 0.003 Ha and tol_fit 1e-6 on bounds 1 % outside the extreme eigenvalues
+    # of H (about 3600 terms; the benchmark's narrower interval of H' takes
+    # 2248), one sum at a mu inside the spectrum; 12 sampled columns against
+    # the oracle's float64 column recursion
     from paper_1704_00512_amd import chess_degree
     s = workload("large80k")
     e0, e1 = g.extreme_eigenvalues(s.pat_h, s.H)
