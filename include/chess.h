@@ -204,12 +204,13 @@ typedef struct {
      * a pass runs half its chain (n_pl / 2 - 1 products) and takes the other
      * moments from Frobenius products of the T_m it computed */
     int32_t moment_products;
-    /* chess_matrix_power, and the S chain of chess_fermi_operator and
-     * chess_eigs_in_interval: Tr W^p of Eq. 6 for the final bounds of S (NaN
-     * if not evaluated, e.g. with sinvhalf_in) and the number of moments it
-     * was judged on: the series' own n_pl_s terms, or, when that is fewer than
-     * Eq. 6 needs on this many rows (chess_degree with CHESS_FN_PENALTY), a
-     * moments-only chain of that many terms run first */
+    /* chess_matrix_power, and the S chain of chess_fermi_operator,
+     * chess_eigs_in_interval and each item of chess_fermi_operator_batched:
+     * Tr W^p of Eq. 6 for the final bounds of S (NaN if not evaluated, e.g.
+     * with sinvhalf_in) and the number of moments it was judged on: the
+     * series' own n_pl_s terms, or, when that is fewer than Eq. 6 needs on
+     * this many rows (chess_degree with CHESS_FN_PENALTY), a moments-only
+     * chain of that many terms run first (in batches always the latter) */
     double s_penalty;
     int32_t s_check_terms;
 } chess_info;
