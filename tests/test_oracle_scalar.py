@@ -114,6 +114,18 @@ def test_degree_consistent_with_paper_inverse_example():
     assert abs(m - g["n_pl_paper"]) <= g["band"]
 
 
+def test_penalty_terms_consistent_with_paper_accuracy_degrees():
+    # Sec. "Accuracy" (inverse of 6000-row matrices, degrees chosen with the
+    # alpha = -200 penalty of Eq. 6): the smallest degree the paper reports,
+    # 60, is where Eq. 6 becomes trustworthy on 6000 rows in reading R7,
+    # while x^-1 itself needs far fewer terms at small condition numbers
+    g = json.load(open(os.path.join(GOLDEN, "paper_accuracy_inverse_degrees.json")))
+    m = cb.penalty_degree(g["n_rows"])
+    assert abs(m - g["n_pl_min_paper"]) <= g["band"]
+    assert cb.penalty_valid(m, g["n_rows"]) and not cb.penalty_valid(m - 8, g["n_rows"])
+    assert cb.degree(cb.power_fn(-1.0), 1.0, 1.5, 1e-12) < g["n_pl_min_paper"] // 2
+
+
 def diag_moments(lam, n_pl):
     th = np.arccos(np.clip(lam, -1, 1))
     return np.array([np.sum(np.cos(k * th)) for k in range(n_pl)])
